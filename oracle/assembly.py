@@ -1,0 +1,183 @@
+"""Oracle: supports, windows, features and the weighted global least-squares rows.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Follows the paper's statement of the discretised problem:
+* ansatz u(x) = sum_j w_j(x) sum_k a_jk phi_jk(x)            (eq. elm_solution)
+* phi_jk = tanh(w_jk . xn + b_jk) on the input normalised to [-1,1] over the
+  subdomain (eq. fcn_depth_h with depth 1; Section 4.2, network architecture)
+* w_j = what_j / sum_i what_i with
+  what_j = prod_d (1 + cos(pi (x_d - mu_jd) / sigma_jd))^2 on |x_d - mu_jd| < sigma_jd
+  (eq. used_window_function_nd, with the parenthesis read as (x - mu)/sigma)
+* row r of M for column (j,k): s_r * Op_r[w_j phi_jk](x_r); h_r = s_r * rhs_r
+  (eq. ELMFBPINN_ls and the component-wise definition of N and B)
+* I_j = rows where w_j(x_r) != 0, blocks M_j = M|_{I_j x K_j}  (eq. DomainDecomp)
+
+Derivatives are written out by hand (chain, product and quotient rules); the
+pins in ``tests/test_oracle_assembly.py`` check them against finite
+differences, partition-of-unity identities and closed forms.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+OP_NEG_LAPLACE, OP_HEAT, OP_HELMHOLTZ, OP_VALUE = 0, 1, 2, 3
+
+
+def support_mask(x: np.ndarray, mu_j: np.ndarray, hw_j: np.ndarray) -> np.ndarray:
+    """Rows strictly inside the open support of subdomain j (all dims |x-mu| < sigma)."""
+    return np.all(np.abs(x - mu_j[None, :]) < hw_j[None, :], axis=1)
+
+
+def incidence(inst):
+    """Row lists I_j (ascending global row ids) for every subdomain j (eq. DomainDecomp)."""
+    return [np.nonzero(support_mask(inst.x, inst.mu[j], inst.hw[j]))[0] for j in range(inst.J)]
+
+
+def window_factor_1d(xd: np.ndarray, mu: float, sig: float):
+    """f = (1 + cos(pi t))^2, t = (x - mu)/sigma, and its first two x-derivatives."""
+    t = (xd - mu) / sig
+    c = 1.0 + np.cos(np.pi * t)
+    s = np.sin(np.pi * t)
+    f = c * c
+    f1 = -(2.0 * np.pi / sig) * s * c
+    f2 = (2.0 * np.pi**2 / sig**2) * (s * s - np.cos(np.pi * t) * c)
+    return f, f1, f2
+
+
+def unnormalised_window(x: np.ndarray, mu_j: np.ndarray, hw_j: np.ndarray):
+    """what_j, d_i what_j, d_ii what_j at rows x (caller restricts x to the support)."""
+    n, d = x.shape
+    fs, f1s, f2s = [], [], []
+    for i in range(d):
+        f, f1, f2 = window_factor_1d(x[:, i], mu_j[i], hw_j[i])
+        fs.append(f)
+        f1s.append(f1)
+        f2s.append(f2)
+    W = np.ones(n)
+    for i in range(d):
+        W = W * fs[i]
+    dW = np.zeros((n, d))
+    ddW = np.zeros((n, d))
+    for i in range(d):
+        others = np.ones(n)
+        for l in range(d):
+            if l != i:
+                others = others * fs[l]
+        dW[:, i] = f1s[i] * others
+        ddW[:, i] = f2s[i] * others
+    return W, dW, ddW
+
+
+def windows(inst, rows_per_block=None):
+    """Normalised windows w_j and their first / pure second derivatives on each block's rows.
+
+    Returns a list over j of (w [m_j], dw [m_j,d], ddw [m_j,d]).  The normaliser
+    sum_i what_i and its derivatives are accumulated over subdomains in ascending i.
+    """
+    if rows_per_block is None:
+        rows_per_block = incidence(inst)
+    N, d = inst.x.shape
+    S = np.zeros(N)
+    dS = np.zeros((N, d))
+    ddS = np.zeros((N, d))
+    local = []
+    for j in range(inst.J):
+        r = rows_per_block[j]
+        W, dW, ddW = unnormalised_window(inst.x[r], inst.mu[j], inst.hw[j])
+        S[r] += W
+        dS[r] += dW
+        ddS[r] += ddW
+        local.append((W, dW, ddW))
+    out = []
+    for j in range(inst.J):
+        r = rows_per_block[j]
+        W, dW, ddW = local[j]
+        s, ds, dds = S[r], dS[r], ddS[r]
+        w = W / s
+        dw = (dW - w[:, None] * ds) / s[:, None]
+        ddw = (ddW - 2.0 * dw * ds - w[:, None] * dds) / s[:, None]
+        out.append((w, dw, ddw))
+    return out
+
+
+def features(x: np.ndarray, mu_j, hw_j, wk: np.ndarray, bk: np.ndarray):
+    """phi = tanh(s), s = sum_i w_i (x_i - mu_i)/sigma_i + b; returns phi, d_i phi, d_ii phi
+    as arrays [m, K], [m, K, d], [m, K, d]."""
+    xn = (x - mu_j[None, :]) / hw_j[None, :]
+    s = xn @ wk.T + bk[None, :]
+    t = np.tanh(s)
+    g = 1.0 - t * t
+    scale = wk / hw_j[None, :]                      # [K, d]: dS/dx_i
+    dphi = g[:, :, None] * scale[None, :, :]
+    ddphi = (-2.0 * t * g)[:, :, None] * (scale * scale)[None, :, :]
+    return t, dphi, ddphi
+
+
+def apply_rowop(op: np.ndarray, psi, dpsi, ddpsi, kappa: float, ksq: float):
+    """Row operator applied to psi = w phi given its derivatives ([m,K], [m,K,d], [m,K,d])."""
+    d = dpsi.shape[2]
+    lap = ddpsi.sum(axis=2)
+    out = np.empty_like(psi)
+    o = op[:, None]
+    # -Laplacian over all input dims
+    out = np.where(o == OP_NEG_LAPLACE, -lap, out)
+    # heat: d_t - kappa * spatial Laplacian, time = last input dim
+    spatial = ddpsi[:, :, : d - 1].sum(axis=2) if d > 1 else np.zeros_like(psi)
+    out = np.where(o == OP_HEAT, dpsi[:, :, d - 1] - kappa * spatial, out)
+    out = np.where(o == OP_HELMHOLTZ, lap + ksq * psi, out)
+    out = np.where(o == OP_VALUE, psi, out)
+    return out
+
+
+def assemble(inst):
+    """Global weighted least-squares system in block form.
+
+    Returns (rows, blocks, h): rows[j] = ascending global row ids I_j,
+    blocks[j] = dense M_j of shape [|I_j|, K_j] (column k = local feature k),
+    h = s_r * rhs_r over all N rows.
+    """
+    rows = incidence(inst)
+    wins = windows(inst, rows)
+    blocks = []
+    for j in range(inst.J):
+        r = rows[j]
+        k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
+        x = inst.x[r]
+        w, dw, ddw = wins[j]
+        phi, dphi, ddphi = features(x, inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1])
+        psi = w[:, None] * phi
+        dpsi = dw[:, None, :] * phi[:, :, None] + w[:, None, None] * dphi
+        ddpsi = (ddw[:, None, :] * phi[:, :, None] + 2.0 * dw[:, None, :] * dphi
+                 + w[:, None, None] * ddphi)
+        Mj = apply_rowop(inst.rowop[r], psi, dpsi, ddpsi, inst.kappa, inst.ksq)
+        blocks.append(inst.weight[r][:, None] * Mj)
+    h = inst.weight * inst.rhs
+    return rows, blocks, h
+
+
+def entry_scale(inst, rows, j):
+    """Sum of absolute values of the terms that make up each entry of M_j (used to size
+    the per-entry rounding tolerance when comparing assemblies)."""
+    r = rows[j]
+    wins = windows(inst, rows)
+    k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
+    w, dw, ddw = wins[j]
+    phi, dphi, ddphi = features(inst.x[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1])
+    a = np.abs
+    psi = a(w)[:, None] * a(phi)
+    dpsi = a(dw)[:, None, :] * a(phi)[:, :, None] + a(w)[:, None, None] * a(dphi)
+    ddpsi = (a(ddw)[:, None, :] * a(phi)[:, :, None] + 2.0 * a(dw)[:, None, :] * a(dphi)
+             + a(w)[:, None, None] * a(ddphi))
+    tot = psi + dpsi.sum(axis=2) + ddpsi.sum(axis=2) * (1.0 + abs(inst.kappa)) + abs(inst.ksq) * psi
+    return a(inst.weight[r])[:, None] * tot
+
+
+def global_dense(inst, rows, blocks):
+    """Dense M (N x sum K_j) from the blocks: M = sum_j V_j^T M_j W_j (eq. DomainDecomp)."""
+    N = inst.N
+    M = np.zeros((N, int(inst.feat_off[-1])))
+    for j in range(inst.J):
+        k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
+        M[np.ix_(rows[j], np.arange(k0, k1))] = blocks[j]
+    return M

@@ -1,0 +1,170 @@
+"""Pins of the oracle's assembly (windows, features, operators, row weights).
+
+Independent checks: hand-derived window values (golden fixture), the partition of
+unity and its derivative identities, central finite differences of the
+value-only ansatz evaluation, and the row-weight convention of eq. ELMFBPINN_ls.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import assembly, solve
+from paper_2506_17626_amd import instances as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tiny_instances():
+    return [I.tiny(n) for n in ("poisson1d", "poisson2d", "heat3d", "helmholtz2d_uneven")]
+
+
+def test_golden_two_window_values():
+    g = json.load(open(os.path.join(GOLDEN, "windows_1d_two_subdomains.json")))
+    inst = I.poisson1d(S=2, K=4, n=4, rho=0.5)
+    assert np.allclose(inst.mu, g["mu"]) and np.allclose(inst.hw, g["hw"])
+    inst.x = np.array(g["points"])[:, None]
+    rows = assembly.incidence(inst)
+    wins = assembly.windows(inst, rows)
+    w0, dw0, ddw0 = wins[0]
+    assert list(rows[0]) == [0, 1, 2]
+    for p in range(3):
+        assert w0[p] == pytest.approx(g["w1"][p], abs=1e-15)
+        if g["dw1"][p] is not None:
+            assert dw0[p, 0] == pytest.approx(g["dw1"][p], abs=1e-13)
+            assert ddw0[p, 0] == pytest.approx(g["ddw1"][p], abs=1e-11)
+
+
+@pytest.mark.parametrize("inst", _tiny_instances(), ids=lambda i: i.name)
+def test_partition_of_unity_and_derivatives(inst):
+    rows = assembly.incidence(inst)
+    wins = assembly.windows(inst, rows)
+    N, d = inst.x.shape
+    S = np.zeros(N)
+    dS = np.zeros((N, d))
+    ddS = np.zeros((N, d))
+    covered = np.zeros(N, bool)
+    for j in range(inst.J):
+        w, dw, ddw = wins[j]
+        S[rows[j]] += w
+        dS[rows[j]] += dw
+        ddS[rows[j]] += ddw
+        covered[rows[j]] = True
+    assert covered.all(), "every collocation point lies in some support"
+    assert np.max(np.abs(S - 1)) < 1e-14
+    # derivatives of a constant sum vanish; the tolerance follows the size of the
+    # individual window-factor terms, |f'| <= 4 pi / sigma and |f''| <= 6 pi^2 / sigma^2
+    smin = inst.hw.min()
+    scale1 = 4 * np.pi / smin * 4 ** (d - 1)
+    scale2 = 6 * np.pi**2 / smin**2 * 4 ** (d - 1)
+    assert np.max(np.abs(dS)) < 1e-13 * scale1
+    assert np.max(np.abs(ddS)) < 1e-12 * scale2
+
+
+def test_window_factor_derivatives_finite_difference():
+    x = np.linspace(0.11, 0.69, 17)
+    mu, sig = 0.4, 0.33
+    f, f1, f2 = assembly.window_factor_1d(x, mu, sig)
+    e = 1e-5
+    fp, _, _ = assembly.window_factor_1d(x + e, mu, sig)
+    fm, _, _ = assembly.window_factor_1d(x - e, mu, sig)
+    assert np.allclose((fp - fm) / (2 * e), f1, rtol=1e-8, atol=1e-6)
+    assert np.allclose((fp - 2 * f + fm) / e**2, f2, rtol=1e-4, atol=1e-3)
+    # closed form at the centre: f=4, f'=0, f''=(2pi^2/s^2)(0 - 1*2)
+    fc, f1c, f2c = assembly.window_factor_1d(np.array([mu]), mu, sig)
+    assert fc[0] == 4.0 and f1c[0] == 0.0
+    assert f2c[0] == pytest.approx(-4 * np.pi**2 / sig**2, rel=1e-15)
+
+
+def test_feature_derivatives_finite_difference():
+    rng = np.random.default_rng(3)
+    d = 3
+    x = rng.uniform(0.2, 0.5, (9, d))
+    mu = np.array([0.3, 0.35, 0.4])
+    hw = np.array([0.2, 0.25, 0.3])
+    wk = rng.uniform(-1, 1, (5, d))
+    bk = rng.uniform(-1, 1, 5)
+    phi, dphi, ddphi = assembly.features(x, mu, hw, wk, bk)
+    assert np.allclose(phi, np.tanh(((x - mu) / hw) @ wk.T + bk), rtol=0, atol=1e-15)
+    e = 1e-5
+    for i in range(d):
+        xp, xm = x.copy(), x.copy()
+        xp[:, i] += e
+        xm[:, i] -= e
+        pp, _, _ = assembly.features(xp, mu, hw, wk, bk)
+        pm, _, _ = assembly.features(xm, mu, hw, wk, bk)
+        assert np.allclose((pp - pm) / (2 * e), dphi[:, :, i], atol=1e-8)
+        assert np.allclose((pp - 2 * phi + pm) / e**2, ddphi[:, :, i], atol=2e-4)
+
+
+def _fd_operator(inst, a, xr, op):
+    """Row operator of the ansatz u_hat = sum a w phi by central differences of the
+    value-only evaluation (an independent code path from the assembled rows)."""
+    d = inst.d
+    e = 2e-4
+    u0 = solve.evaluate(inst, a, xr)
+    lap = np.zeros(len(xr))
+    first = np.zeros((len(xr), d))
+    for i in range(d):
+        xp, xm = xr.copy(), xr.copy()
+        xp[:, i] += e
+        xm[:, i] -= e
+        up, um = solve.evaluate(inst, a, xp), solve.evaluate(inst, a, xm)
+        first[:, i] = (up - um) / (2 * e)
+        lap += (up - 2 * u0 + um) / e**2 if (op != I.OP_HEAT or i < d - 1) else 0.0
+    if op == I.OP_NEG_LAPLACE:
+        return -lap
+    if op == I.OP_HEAT:
+        return first[:, d - 1] - inst.kappa * lap
+    if op == I.OP_HELMHOLTZ:
+        return lap + inst.ksq * u0
+    return u0
+
+
+@pytest.mark.parametrize("name", ["poisson1d", "poisson2d", "heat3d", "helmholtz2d_uneven"])
+def test_assembled_rows_match_finite_difference_operator(name):
+    inst = I.tiny(name)
+    rows, blocks, h = assembly.assemble(inst)
+    M = assembly.global_dense(inst, rows, blocks)
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal(M.shape[1]) * 0.01
+    Ma = M @ a
+    # interior rows away from the domain boundary (central differences need room)
+    interior = np.all((inst.x > 0.01) & (inst.x < 0.99), axis=1)
+    pick = np.nonzero(interior)[0][:: max(1, interior.sum() // 25)]
+    op = inst.rowop[pick[0]]
+    assert np.all(inst.rowop[pick] == op)
+    fd = _fd_operator(inst, a, inst.x[pick], op)
+    got = Ma[pick] / inst.weight[pick]
+    scale = np.abs(got).max()
+    assert np.max(np.abs(got - fd)) < 2e-4 * scale
+    # boundary / initial rows are plain values of the ansatz
+    vrows = np.nonzero(inst.rowop == I.OP_VALUE)[0]
+    val = solve.evaluate(inst, a, inst.x[vrows])
+    assert np.allclose(Ma[vrows] / inst.weight[vrows], val, rtol=1e-12, atol=1e-14)
+
+
+def test_row_weights_and_rhs_scaling():
+    inst = I.tiny("heat3d")
+    _, _, h = assembly.assemble(inst)
+    NI = np.sum(inst.rowop == I.OP_HEAT)
+    assert np.allclose(inst.weight[inst.rowop == I.OP_HEAT], 1 / np.sqrt(NI))
+    # two boundary sets (initial condition, lateral faces), each weighted by 1/sqrt(N_B^(l))
+    nb = inst.meta["nb"] ** 2
+    assert np.allclose(inst.weight[NI:NI + nb], 1 / np.sqrt(nb))
+    assert np.allclose(inst.weight[NI + nb:], 1 / np.sqrt(4 * nb))
+    assert np.array_equal(h, inst.weight * inst.rhs)
+
+
+def test_incidence_strict_support_and_cover_bound():
+    inst = I.tiny("poisson2d")
+    rows = assembly.incidence(inst)
+    for j, r in enumerate(rows):
+        assert np.all(np.diff(r) > 0)
+        inside = np.all(np.abs(inst.x[r] - inst.mu[j]) < inst.hw[j], axis=1)
+        assert inside.all()
+    cover = np.zeros(inst.N, int)
+    for r in rows:
+        cover[r] += 1
+    assert cover.max() <= 2 ** inst.d     # overlap fraction < 1/2
