@@ -1,0 +1,218 @@
+/*
+ * rfm.h -- C ABI of the MI355X (gfx950) hot path of block sigma-RRQR filtering and
+ * right-preconditioned LSQR for ELM-FBPINN least-squares systems.
+ *
+ * The method (van Beek, Dolean, Moseley, "Local feature filtering for scalable and
+ * well-conditioned domain-decomposed random feature methods"):
+ *   - the weighted least-squares system min ||M a - h|| of eq. ELMFBPINN_ls, with
+ *     M = sum_j V_j^T M_j W_j block-sparse over overlapping subdomains (eq. DomainDecomp);
+ *   - every block M_j is filtered by a sigma-RRQR factorisation (Algorithm 1), the
+ *     threshold taken relative to the leading diagonal entry of R_j;
+ *   - the filtered system is right-preconditioned by S^{-1} = sum_j W_j^T R_j^{-1} W_j,
+ *     which makes M_hat S^{-1} = sum_j V_j^T Q_hat_j W_hat_j (Proposition 3.1), and solved
+ *     by LSQR; a = S^{-1} y with zeros at the dropped columns (Algorithm 2).
+ *
+ * Conventions shared by every call:
+ *   - "device" pointers are HIP device memory (gfx950) owned by the caller; "host"
+ *     pointers are ordinary host memory owned by the caller.  The library keeps no
+ *     allocation between calls, except where a call says otherwise.
+ *   - Every call validates its arguments on the host before launching anything; on
+ *     RFM_EINVAL / RFM_EUNSUPPORTED no output has been touched.  On RFM_EHIP outputs
+ *     are undefined.  rfm_last_error() returns a description of the last failure on
+ *     the calling thread.
+ *   - Calls taking a stream enqueue their work on it and return without waiting,
+ *     unless marked (sync).
+ *   - Floating point is IEEE binary64 throughout this header.
+ */
+#ifndef RFM_H
+#define RFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RFM_OK = 0,
+  RFM_EINVAL = 1,         /* invalid argument (null pointer, bad size, inconsistent layout) */
+  RFM_EHIP = 3,           /* a HIP runtime call failed */
+  RFM_ENOTCONV = 4,       /* LSQR reached maxit; outputs hold the last iterate */
+  RFM_EUNSUPPORTED = 5    /* sizes beyond what the kernels are built for */
+} rfm_status;
+
+/* Row operators (the linear PDE / boundary operators N and B_l of Section 2.1).
+ * Inputs x have d coordinates; for RFM_OP_HEAT the last coordinate is time. */
+typedef enum {
+  RFM_OP_NEG_LAPLACE = 0, /* -sum_i d_ii u                          */
+  RFM_OP_HEAT = 1,        /* d_t u - kappa * sum_{i<d-1} d_ii u       */
+  RFM_OP_HELMHOLTZ = 2,   /* sum_i d_ii u + ksq * u                   */
+  RFM_OP_VALUE = 3        /* u (Dirichlet and initial-condition rows)  */
+} rfm_rowop;
+
+/* Block layout of the global matrix (eq. DomainDecomp).  Produced on the host by
+ * rfm_plan; the caller copies the arrays to the device and fills the pointers.
+ *   I_j  = rows r with |x_r,i - mu_j,i| < hw_j,i for every i (open support of the
+ *          window), ascending;
+ *   block j of M, Q: column-major |I_j| x K_j at element offset blk_off[j]
+ *          (column k = local feature k, leading dimension |I_j|);
+ *   block j of R:    column-major K_j x K_j at element offset rsq_off[j];
+ *   per-feature vectors (kept, y, a): entry (j,k) at feat_off[j] + k. */
+typedef struct {
+  int32_t d;              /* input dimension (1..3)                          */
+  int32_t J;              /* number of subdomains                           */
+  int64_t N;              /* rows of the global system                      */
+  int64_t nnz_rows;       /* sum_j |I_j|                                    */
+  int64_t nnz;            /* sum_j |I_j| K_j                                */
+  int64_t ncols;          /* sum_j K_j                                      */
+  int64_t nrsq;           /* sum_j K_j^2                                    */
+  int32_t max_rows;       /* max_j |I_j|                                    */
+  int32_t max_cols;       /* max_j K_j                                      */
+  const int64_t *row_off; /* device [J+1] prefix sums of |I_j|              */
+  const int32_t *rows;    /* device [nnz_rows] global row ids, block-major  */
+  const int32_t *inc_blk; /* device [nnz_rows] block id of each incidence   */
+  const int64_t *rinc_off;/* device [N+1] per-row incidence ranges          */
+  const int64_t *rinc;    /* device [nnz_rows] incidence ids per row, ascending j */
+  const int64_t *feat_off;/* device [J+1] prefix sums of K_j                */
+  const int64_t *blk_off; /* device [J+1] prefix sums of |I_j| K_j          */
+  const int64_t *rsq_off; /* device [J+1] prefix sums of K_j^2              */
+} rfm_layout;
+
+/* Discretised problem (Section 2.1 and Section 4.2): subdomain geometry, random
+ * features phi_jk = tanh(w_jk . (x - mu_j)/hw_j + b_jk) (eq. fcn_depth_h, depth 1,
+ * inputs normalised to [-1,1] per subdomain), points and per-row data. */
+typedef struct {
+  const double *x;        /* device [N*d] row-major points                 */
+  const int32_t *rowop;   /* device [N] rfm_rowop per row                  */
+  const double *weight;   /* device [N] row scale s_r (1/sqrt(N_I), sqrt(lambda_l/N_B^(l))) */
+  const double *rhs;      /* device [N] unscaled right-hand side f or g_l  */
+  const double *mu;       /* device [J*d] subdomain centres                */
+  const double *hw;       /* device [J*d] subdomain half-widths            */
+  const double *w;        /* device [ncols*d] feature weights              */
+  const double *b;        /* device [ncols] feature biases                 */
+  double kappa;           /* RFM_OP_HEAT diffusion constant                */
+  double ksq;             /* RFM_OP_HELMHOLTZ k^2                          */
+} rfm_problem;
+
+/* Planning (sync, host only).  Builds the supports I_j of eq. DomainDecomp from host
+ * copies of the points (x [N*d]), centres and half-widths (mu, hw [J*d]) and the
+ * feature counts (K [J]).  Membership uses the strict test |x - mu| < hw in binary64.
+ * Call once with all array outputs NULL to get the sizes in *sizes_out
+ * ([0]=nnz_rows, [1]=nnz, [2]=ncols, [3]=nrsq, [4]=max_rows, [5]=max_cols); then call
+ * again with arrays of those sizes: row_off, feat_off, blk_off, rsq_off [J+1],
+ * rows, inc_blk, rinc [nnz_rows], rinc_off [N+1]. */
+rfm_status rfm_plan(int32_t d, int32_t J, int64_t N, const double *x, const double *mu,
+                    const double *hw, const int32_t *K, int64_t *sizes_out,
+                    int64_t *row_off, int32_t *rows, int32_t *inc_blk, int64_t *rinc_off,
+                    int64_t *rinc, int64_t *feat_off, int64_t *blk_off, int64_t *rsq_off);
+
+/* Bytes of device workspace rfm_assemble needs for this layout. */
+size_t rfm_assemble_ws_bytes(const rfm_layout *L);
+
+/* Assembly of the weighted system (eq. ELMFBPINN_ls with the component-wise
+ * definition of N and B): M[(r in I_j),(j,k)] = s_r * Op_r[w_j phi_jk](x_r) with the
+ * partition-of-unity window w_j = what_j / sum_i what_i,
+ * what_j = prod_i (1 + cos(pi (x_i - mu_ji)/hw_ji))^2 (eq. used_window_function_nd),
+ * and h_r = s_r * rhs_r.  Outputs: M device [nnz] in the block layout, h device [N]. */
+rfm_status rfm_assemble(const rfm_layout *L, const rfm_problem *P, double *M, double *h,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace rfm_rrqr_filter needs for this layout. */
+size_t rfm_rrqr_ws_bytes(const rfm_layout *L);
+
+/* sigma-RRQR filter of every block (Algorithm 1), one workgroup per block:
+ * column-pivoted Householder QR (at each step the column with the largest norm
+ * orthogonal to the columns already chosen; bit-equal norms go to the smallest
+ * local feature id), stopping at the first step s with |R_ss| <= tau * |R_00|
+ * (threshold relative to the leading diagonal of R_j).  tau in [0, 1).
+ * Inputs:  M device [nnz] (not modified).
+ * Outputs: rank device [J]        r_j (0 <= r_j <= min(|I_j|, K_j));
+ *          kept device [ncols]    kept local feature ids in pivot order, entries
+ *                                 k < r_j of block j used, the rest set to -1;
+ *          R    device [nrsq]     upper-triangular R_hat_j (r_j x r_j, positive
+ *                                 diagonal, in the block's K_j x K_j slot);
+ *          Q    device [nnz]      explicit Q_hat_j (first r_j columns of the block's
+ *                                 slot, orthonormal, Q_hat_j R_hat_j = M_j[:, kept]);
+ *          ratios device [ncols]  nullable; |R_ss|/|R_00| for every step taken, the
+ *                                 stopping step included, 0 elsewhere.
+ * Sizes: max_rows <= 3072 and max_cols <= 2048 (RFM_EUNSUPPORTED otherwise). */
+rfm_status rfm_rrqr_filter(const rfm_layout *L, const double *M, double tau, int32_t *rank,
+                           int32_t *kept, double *R, double *Q, double *ratios, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* Operator of the preconditioned system M_hat S^{-1} (Proposition 3.1). */
+typedef enum {
+  RFM_FORM_Q = 0,         /* explicit Q_hat_j: A = sum_j V_j^T Q_hat_j W_hat_j        */
+  RFM_FORM_R = 1          /* kept columns of M_j with back-substitution by R_hat_j   */
+} rfm_form;
+
+typedef struct {
+  int32_t form;           /* rfm_form                                       */
+  const int32_t *rank;    /* device [J]                                     */
+  const double *Q;        /* device [nnz]  (RFM_FORM_Q)                     */
+  const double *M;        /* device [nnz]  (RFM_FORM_R)                     */
+  const int32_t *kept;    /* device [ncols] (RFM_FORM_R)                    */
+  const double *R;        /* device [nrsq] (RFM_FORM_R)                     */
+} rfm_operator;
+
+/* Device time of the iteration kernels of one solve, measured with HIP events recorded
+ * around every launch on the solve's stream (filled only when requested). */
+typedef struct {
+  double ms[4];           /* total ms of: forward block products, row gather, adjoint block
+                             products (+ rotation), y/w update (+ stop test) */
+  int64_t launches[4];    /* launches counted (iterations that ran, not the no-op tail) */
+} rfm_kernel_times;
+
+typedef struct {
+  double atol, btol;      /* stopping tolerances (see rfm_lsqr_solve)       */
+  int64_t maxit;          /* iteration limit (>= 1)                         */
+  int32_t check_every;    /* iterations launched between host checks of the stop flag (>= 1) */
+  int32_t use_graph;      /* 1: replay the per-check batch of launches as a HIP graph */
+  rfm_kernel_times *times;/* host, nullable: per-kernel device times of the iterations */
+} rfm_lsqr_opts;
+
+typedef struct {
+  int64_t iters;          /* iterations performed                            */
+  int32_t stop;           /* 1: S1, 2: S2, 3: maxit, 4: breakdown (exact solution) */
+  double rnorm_est;       /* ||r|| estimate at the stop                      */
+  double artnorm_est;     /* ||A^T r|| estimate at the stop                  */
+  double anorm;           /* ||A|| used by the rule: sqrt(sum_j r_j)         */
+  double hnorm;           /* ||h||                                           */
+  double ynorm;           /* ||y|| at the stop                               */
+  double relres;          /* explicit ||h - A y|| / ||h|| recomputed at the stop */
+  double eta;             /* explicit ||A^T r|| / (||A|| ||r||) recomputed at the stop */
+} rfm_lsqr_info;
+
+/* Bytes of device workspace rfm_lsqr_solve needs for this layout. */
+size_t rfm_lsqr_ws_bytes(const rfm_layout *L);
+
+/* LSQR (Paige and Saunders 1982) on min ||A y - h|| with A the preconditioned operator
+ * (Algorithm 2, solve step), started from y0 (nullable = 0).  Stopping rule, with the
+ * fixed ||A|| = ||A||_F = sqrt(sum_j r_j):
+ *   S1: ||r|| <= btol ||h|| + atol ||A|| ||y||,   S2: ||A^T r|| <= atol ||A|| ||r||,
+ * on the recurrence estimates; breakdown (alpha or beta = 0) stops with the exact
+ * solution.  After stopping the residuals are recomputed explicitly with the operator
+ * and returned in info.
+ * Vectors: h device [N]; y0, y device [ncols] (entry (j,k) for k < r_j at feat_off[j]+k
+ * in pivot order; other entries of y are set to 0).  (sync): returns after the solve;
+ * RFM_ENOTCONV if maxit was reached. */
+rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A, const double *h,
+                          const double *y0, const rfm_lsqr_opts *opts, double *y,
+                          rfm_lsqr_info *info, void *ws, size_t ws_bytes, void *stream);
+
+/* Back-substitution a_hat_j = R_hat_j^{-1} y_j and scatter to the global coefficient
+ * vector with zeros at dropped columns (Algorithm 2, output step).
+ * y device [ncols] (layout of rfm_lsqr_solve), a device [ncols] (entry (j,k) at
+ * feat_off[j] + k, local feature order). */
+rfm_status rfm_coefficients(const rfm_layout *L, const int32_t *rank, const int32_t *kept,
+                            const double *R, const double *y, double *a, void *stream);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *rfm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFM_H */

@@ -156,21 +156,76 @@ def assemble(inst):
     return rows, blocks, h
 
 
-def entry_scale(inst, rows, j):
-    """Sum of absolute values of the terms that make up each entry of M_j (used to size
-    the per-entry rounding tolerance when comparing assemblies)."""
+def entry_error_scale(inst, rows, j):
+    """Magnitude that bounds the rounding error of every entry of M_j.
+
+    The entry formula is re-evaluated with every intermediate replaced by the sum of
+    the absolute values of its terms (|a - b| -> |a| + |b|, |a b| -> |a| |b|), the
+    usual running bound of forward rounding-error analysis: an evaluation of the
+    formula in binary64 with n rounded operations on the path to an entry differs from
+    the exact value by at most about n u times this magnitude.  tanh contributes its
+    condition number: |d tanh(s)| <= (1 - t^2)|ds| + |t| u.
+    """
+    d = inst.d
+    N = inst.N
+    # absolute-value evaluation of the windows and of their normaliser
+    S = np.zeros(N)
+    dSa = np.zeros((N, d))
+    ddSa = np.zeros((N, d))
+    parts = []
+    for i in range(inst.J):
+        r = rows[i]
+        x = inst.x[r]
+        f_a, f1_a, f2_a = [], [], []
+        W = np.ones(len(r))
+        for a in range(d):
+            sig = inst.hw[i, a]
+            t = (x[:, a] - inst.mu[i, a]) / sig
+            cs = np.abs(np.cos(np.pi * t))
+            sn = np.abs(np.sin(np.pi * t))
+            c_true = 1.0 + np.cos(np.pi * t)
+            W = W * c_true * c_true
+            f_a.append((1.0 + cs) ** 2)
+            f1_a.append((2.0 * np.pi / sig) * sn * (1.0 + cs))
+            f2_a.append((2.0 * np.pi**2 / sig**2) * (sn * sn + cs * (1.0 + cs)))
+        Wa = np.prod(f_a, axis=0)
+        dWa = np.zeros((len(r), d))
+        ddWa = np.zeros((len(r), d))
+        for a in range(d):
+            others = np.prod([f_a[l] for l in range(d) if l != a], axis=0) if d > 1 else np.ones(len(r))
+            dWa[:, a] = f1_a[a] * others
+            ddWa[:, a] = f2_a[a] * others
+        S[r] += W
+        dSa[r] += dWa
+        ddSa[r] += ddWa
+        parts.append((Wa, dWa, ddWa))
     r = rows[j]
-    wins = windows(inst, rows)
+    Wa, dWa, ddWa = parts[j]
+    s = S[r]
+    wa = Wa / s
+    dwa = (dWa + wa[:, None] * dSa[r]) / s[:, None]
+    ddwa = (ddWa + 2.0 * dwa * dSa[r] + wa[:, None] * ddSa[r]) / s[:, None]
     k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
-    w, dw, ddw = wins[j]
-    phi, dphi, ddphi = features(inst.x[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1])
-    a = np.abs
-    psi = a(w)[:, None] * a(phi)
-    dpsi = a(dw)[:, None, :] * a(phi)[:, :, None] + a(w)[:, None, None] * a(dphi)
-    ddpsi = (a(ddw)[:, None, :] * a(phi)[:, :, None] + 2.0 * a(dw)[:, None, :] * a(dphi)
-             + a(w)[:, None, None] * a(ddphi))
-    tot = psi + dpsi.sum(axis=2) + ddpsi.sum(axis=2) * (1.0 + abs(inst.kappa)) + abs(inst.ksq) * psi
-    return a(inst.weight[r])[:, None] * tot
+    wk, bk = inst.w[k0:k1], inst.b[k0:k1]
+    xn = (inst.x[r] - inst.mu[j][None, :]) / inst.hw[j][None, :]
+    sarg = np.abs(xn) @ np.abs(wk).T + np.abs(bk)[None, :]
+    t = np.tanh(xn @ wk.T + bk[None, :])
+    g = 1.0 - t * t
+    ta = np.abs(t) + g * sarg
+    ga = 1.0 + t * t + 2.0 * np.abs(t) * g * sarg
+    sc = np.abs(wk / inst.hw[j][None, :])
+    dphia = ga[:, :, None] * sc[None, :, :]
+    ddphia = (2.0 * ta * ga)[:, :, None] * (sc * sc)[None, :, :]
+    psia = wa[:, None] * ta
+    dpsia = dwa[:, None, :] * ta[:, :, None] + wa[:, None, None] * dphia
+    ddpsia = ddwa[:, None, :] * ta[:, :, None] + 2.0 * dwa[:, None, :] * dphia + wa[:, None, None] * ddphia
+    lap = ddpsia.sum(axis=2)
+    op = inst.rowop[r][:, None]
+    out = np.where(op == OP_NEG_LAPLACE, lap, psia)
+    spatial = ddpsia[:, :, : d - 1].sum(axis=2) if d > 1 else np.zeros_like(psia)
+    out = np.where(op == OP_HEAT, dpsia[:, :, d - 1] + abs(inst.kappa) * spatial, out)
+    out = np.where(op == OP_HELMHOLTZ, lap + abs(inst.ksq) * psia, out)
+    return np.abs(inst.weight[r])[:, None] * out
 
 
 def global_dense(inst, rows, blocks):

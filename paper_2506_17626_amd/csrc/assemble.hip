@@ -1,0 +1,209 @@
+// Assembly of the weighted ELM-FBPINN least-squares system on gfx950.
+//
+// window_table: one thread per global row r.  Walks the subdomains covering r in
+//   ascending j, accumulates the unnormalised windows what_j and their first and pure
+//   second derivatives, then writes the normalised window w_j = what_j / sum_i what_i
+//   and its derivatives (quotient rule) for every incidence (j, r) -- the partition of
+//   unity of eq. used_window_function_nd -- and h_r = s_r rhs_r (eq. ELMFBPINN_ls).
+// assemble_entries: lane <-> row of one block, so the column-major block is written
+//   with coalesced 64-wide stores; each thread produces a run of features for its row,
+//   reusing the row's point and window data.  Entry = s_r Op_r[w_j phi_jk](x_r) by the
+//   product rule with phi = tanh(w . xn + b), xn = (x - mu_j)/hw_j (eq. fcn_depth_h).
+#include "common.hpp"
+
+namespace rfm {
+namespace {
+
+constexpr int kRowsPerBlock = 256;
+constexpr int kFeatPerThread = 32;
+
+template <int D>
+__device__ __forceinline__ void window_factors(const double *xr, const double *mu,
+                                               const double *hw, double &W, double *dW,
+                                               double *ddW) {
+  const double pi = 3.141592653589793;
+  double f[D], f1[D], f2[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double t = (xr[i] - mu[i]) / hw[i];
+    const double cs = cos(pi * t);
+    const double c = 1.0 + cs;
+    const double s = sin(pi * t);
+    f[i] = c * c;
+    f1[i] = -(2.0 * pi / hw[i]) * s * c;
+    f2[i] = (2.0 * pi * pi / (hw[i] * hw[i])) * (s * s - cs * c);
+  }
+  W = 1.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) W *= f[i];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double others = 1.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l)
+      if (l != i) others *= f[l];
+    dW[i] = f1[i] * others;
+    ddW[i] = f2[i] * others;
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void window_table(rfm_layout L, rfm_problem P, double *win,
+                                                    double *h) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= L.N) return;
+  h[r] = P.weight[r] * P.rhs[r];
+  double xr[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) xr[i] = P.x[r * D + i];
+  double S = 0.0, dS[D], ddS[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) dS[i] = ddS[i] = 0.0;
+  const int64_t q0 = L.rinc_off[r], q1 = L.rinc_off[r + 1];
+  for (int64_t q = q0; q < q1; ++q) {
+    const int64_t p = L.rinc[q];
+    const int32_t j = L.inc_blk[p];
+    double W, dW[D], ddW[D];
+    window_factors<D>(xr, P.mu + (int64_t)j * D, P.hw + (int64_t)j * D, W, dW, ddW);
+    S += W;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      dS[i] += dW[i];
+      ddS[i] += ddW[i];
+    }
+  }
+  for (int64_t q = q0; q < q1; ++q) {
+    const int64_t p = L.rinc[q];
+    const int32_t j = L.inc_blk[p];
+    double W, dW[D], ddW[D];
+    window_factors<D>(xr, P.mu + (int64_t)j * D, P.hw + (int64_t)j * D, W, dW, ddW);
+    const double w = W / S;
+    double *out = win + p * (1 + 2 * D);
+    out[0] = w;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double dw = (dW[i] - w * dS[i]) / S;
+      out[1 + i] = dw;
+      out[1 + D + i] = (ddW[i] - 2.0 * dw * dS[i] - w * ddS[i]) / S;
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, rfm_problem P,
+                                                                  const double *win, double *M) {
+  const int j = blockIdx.z;
+  const int64_t r0 = L.row_off[j];
+  const int m = (int)(L.row_off[j + 1] - r0);
+  const int i = blockIdx.x * kRowsPerBlock + threadIdx.x;
+  const int64_t f0 = L.feat_off[j];
+  const int K = (int)(L.feat_off[j + 1] - f0);
+  const int k0 = blockIdx.y * kFeatPerThread;
+  if (i >= m || k0 >= K) return;
+  const int64_t p = r0 + i;
+  const int32_t r = L.rows[p];
+  double xn[D], hwj[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double h = P.hw[(int64_t)j * D + a];
+    xn[a] = (P.x[(int64_t)r * D + a] - P.mu[(int64_t)j * D + a]) / h;
+    hwj[a] = h;
+  }
+  const double *wp = win + p * (1 + 2 * D);
+  const double w = wp[0];
+  double dw[D], ddw[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    dw[a] = wp[1 + a];
+    ddw[a] = wp[1 + D + a];
+  }
+  const int op = P.rowop[r];
+  const double sr = P.weight[r];
+  const double kappa = P.kappa, ksq = P.ksq;
+  double *out = M + L.blk_off[j] + (int64_t)i;
+  const int k1 = min(K, k0 + kFeatPerThread);
+  for (int k = k0; k < k1; ++k) {
+    const double *wk = P.w + (f0 + k) * D;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) s += xn[a] * wk[a];
+    s += P.b[f0 + k];
+    const double t = tanh(s);
+    const double g = 1.0 - t * t;
+    const double psi = w * t;
+    double lap = 0.0, spatial = 0.0, dlast = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double sc = wk[a] / hwj[a];
+      const double dphi = g * sc;
+      const double ddphi = (-2.0 * t * g) * (sc * sc);
+      const double dpsi = dw[a] * t + w * dphi;
+      const double ddpsi = ddw[a] * t + 2.0 * dw[a] * dphi + w * ddphi;
+      lap += ddpsi;
+      if (a < D - 1) spatial += ddpsi;
+      if (a == D - 1) dlast = dpsi;
+    }
+    double v;
+    switch (op) {
+      case RFM_OP_NEG_LAPLACE: v = -lap; break;
+      case RFM_OP_HEAT: v = dlast - kappa * (D > 1 ? spatial : 0.0); break;
+      case RFM_OP_HELMHOLTZ: v = lap + ksq * psi; break;
+      default: v = psi; break;
+    }
+    out[(int64_t)k * m] = sr * v;
+  }
+}
+
+template <int D>
+rfm_status launch(const rfm_layout *L, const rfm_problem *P, double *M, double *h, double *win,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(window_table<D>, dim3(ceil_div(L->N, 256)), dim3(256), 0, st, *L, *P, win, h);
+  RFM_LAUNCH_CHECK();
+  if (L->max_rows > 0 && L->max_cols > 0) {
+    dim3 grid(ceil_div(L->max_rows, kRowsPerBlock), ceil_div(L->max_cols, kFeatPerThread), L->J);
+    hipLaunchKernelGGL(assemble_entries<D>, grid, dim3(kRowsPerBlock), 0, st, *L, *P, win, M);
+    RFM_LAUNCH_CHECK();
+  }
+  return RFM_OK;
+}
+
+}  // namespace
+
+rfm_status check_layout(const rfm_layout *L, const char *who) {
+  if (!L) return fail(RFM_EINVAL, std::string(who) + ": null layout");
+  if (L->d < 1 || L->d > 3) return fail(RFM_EINVAL, std::string(who) + ": d must be 1..3");
+  if (L->J < 1 || L->N < 1) return fail(RFM_EINVAL, std::string(who) + ": empty layout");
+  if (L->J > 65535) return fail(RFM_EUNSUPPORTED, std::string(who) + ": J > 65535");
+  if (!L->row_off || !L->rows || !L->inc_blk || !L->rinc_off || !L->rinc || !L->feat_off ||
+      !L->blk_off || !L->rsq_off)
+    return fail(RFM_EINVAL, std::string(who) + ": null layout array");
+  if (L->max_rows < 0 || L->max_cols < 0 || L->nnz < 0 || L->ncols < 0)
+    return fail(RFM_EINVAL, std::string(who) + ": negative size");
+  return RFM_OK;
+}
+
+}  // namespace rfm
+
+extern "C" size_t rfm_assemble_ws_bytes(const rfm_layout *L) {
+  if (!L) return 0;
+  return (size_t)L->nnz_rows * (1 + 2 * (size_t)L->d) * sizeof(double);
+}
+
+extern "C" rfm_status rfm_assemble(const rfm_layout *L, const rfm_problem *P, double *M, double *h,
+                                   void *ws, size_t ws_bytes, void *stream) {
+  using namespace rfm;
+  rfm_status s = check_layout(L, "rfm_assemble");
+  if (s != RFM_OK) return s;
+  if (!P || !P->x || !P->rowop || !P->weight || !P->rhs || !P->mu || !P->hw || !P->w || !P->b)
+    return fail(RFM_EINVAL, "rfm_assemble: null problem array");
+  if (!h || (L->nnz > 0 && !M)) return fail(RFM_EINVAL, "rfm_assemble: null output");
+  if (ws_bytes < rfm_assemble_ws_bytes(L) || (rfm_assemble_ws_bytes(L) > 0 && !ws))
+    return fail(RFM_EINVAL, "rfm_assemble: workspace too small");
+  hipStream_t st = (hipStream_t)stream;
+  double *win = (double *)ws;
+  switch (L->d) {
+    case 1: return launch<1>(L, P, M, h, win, st);
+    case 2: return launch<2>(L, P, M, h, win, st);
+    default: return launch<3>(L, P, M, h, win, st);
+  }
+}

@@ -1,0 +1,237 @@
+"""Python binding of librfm.so (ctypes): argument marshalling only.
+
+Every computation runs in the HIP library; this module allocates device tensors with
+PyTorch (the caching allocator is the memory manager, the current torch stream is the
+HIP stream) and passes raw pointers through the C ABI declared in include/rfm.h.
+Importing it raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "librfm.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"librfm.so not built ({_LIB_PATH}); run python -m paper_2506_17626_amd.build")
+_lib = C.CDLL(_LIB_PATH)
+
+RFM_OK, RFM_EINVAL, RFM_EHIP, RFM_ENOTCONV, RFM_EUNSUPPORTED = 0, 1, 3, 4, 5
+FORM_Q, FORM_R = 0, 1
+
+_p = C.c_void_p
+_i64p = C.POINTER(C.c_int64)
+_i32p = C.POINTER(C.c_int32)
+_dp = C.POINTER(C.c_double)
+
+
+class Layout(C.Structure):
+    _fields_ = [("d", C.c_int32), ("J", C.c_int32), ("N", C.c_int64), ("nnz_rows", C.c_int64),
+                ("nnz", C.c_int64), ("ncols", C.c_int64), ("nrsq", C.c_int64),
+                ("max_rows", C.c_int32), ("max_cols", C.c_int32),
+                ("row_off", _p), ("rows", _p), ("inc_blk", _p), ("rinc_off", _p), ("rinc", _p),
+                ("feat_off", _p), ("blk_off", _p), ("rsq_off", _p)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("x", _p), ("rowop", _p), ("weight", _p), ("rhs", _p), ("mu", _p), ("hw", _p),
+                ("w", _p), ("b", _p), ("kappa", C.c_double), ("ksq", C.c_double)]
+
+
+class Operator(C.Structure):
+    _fields_ = [("form", C.c_int32), ("rank", _p), ("Q", _p), ("M", _p), ("kept", _p), ("R", _p)]
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+    NAMES = ("fwd_local", "fwd_gather", "adj_local", "yw_update")
+
+    def as_dict(self):
+        return {n: dict(ms=self.ms[k], launches=self.launches[k]) for k, n in enumerate(self.NAMES)}
+
+
+class LsqrOpts(C.Structure):
+    _fields_ = [("atol", C.c_double), ("btol", C.c_double), ("maxit", C.c_int64),
+                ("check_every", C.c_int32), ("use_graph", C.c_int32),
+                ("times", C.POINTER(KernelTimes))]
+
+
+class LsqrInfo(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("stop", C.c_int32), ("rnorm_est", C.c_double),
+                ("artnorm_est", C.c_double), ("anorm", C.c_double), ("hnorm", C.c_double),
+                ("ynorm", C.c_double), ("relres", C.c_double), ("eta", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib.rfm_plan.restype = C.c_int
+_lib.rfm_plan.argtypes = [C.c_int32, C.c_int32, C.c_int64, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p,
+                          _p, _p, _p]
+_lib.rfm_assemble_ws_bytes.restype = C.c_size_t
+_lib.rfm_assemble_ws_bytes.argtypes = [C.POINTER(Layout)]
+_lib.rfm_assemble.restype = C.c_int
+_lib.rfm_assemble.argtypes = [C.POINTER(Layout), C.POINTER(Problem), _p, _p, _p, C.c_size_t, _p]
+_lib.rfm_rrqr_ws_bytes.restype = C.c_size_t
+_lib.rfm_rrqr_ws_bytes.argtypes = [C.POINTER(Layout)]
+_lib.rfm_rrqr_filter.restype = C.c_int
+_lib.rfm_rrqr_filter.argtypes = [C.POINTER(Layout), _p, C.c_double, _p, _p, _p, _p, _p, _p,
+                                 C.c_size_t, _p]
+_lib.rfm_lsqr_ws_bytes.restype = C.c_size_t
+_lib.rfm_lsqr_ws_bytes.argtypes = [C.POINTER(Layout)]
+_lib.rfm_lsqr_solve.restype = C.c_int
+_lib.rfm_lsqr_solve.argtypes = [C.POINTER(Layout), C.POINTER(Operator), _p, _p, C.POINTER(LsqrOpts),
+                                _p, C.POINTER(LsqrInfo), _p, C.c_size_t, _p]
+_lib.rfm_coefficients.restype = C.c_int
+_lib.rfm_coefficients.argtypes = [C.POINTER(Layout), _p, _p, _p, _p, _p, _p]
+_lib.rfm_last_error.restype = C.c_char_p
+_lib.rfm_last_error.argtypes = []
+
+EXPORTED = ["rfm_plan", "rfm_assemble_ws_bytes", "rfm_assemble", "rfm_rrqr_ws_bytes",
+            "rfm_rrqr_filter", "rfm_lsqr_ws_bytes", "rfm_lsqr_solve", "rfm_coefficients",
+            "rfm_last_error"]
+
+
+class RfmError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: status {status}: {_lib.rfm_last_error().decode()}")
+        self.status = status
+
+
+def _check(status, where, allow=()):
+    if status != RFM_OK and status not in allow:
+        raise RfmError(status, where)
+    return status
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Plan:
+    """Host plan (numpy) plus its device copies and the C layout struct."""
+    layout: Layout
+    host: dict
+    dev: dict
+
+    @property
+    def J(self):
+        return self.layout.J
+
+
+def rfm_plan(d, J, x, mu, hw, K, device="cuda") -> Plan:
+    """Supports and block layout (host planning; arrays are copied to `device`)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    hw = np.ascontiguousarray(hw, dtype=np.float64)
+    K = np.ascontiguousarray(K, dtype=np.int32)
+    N = x.shape[0]
+    sizes = np.zeros(6, dtype=np.int64)
+    nul = [None] * 8
+    _check(_lib.rfm_plan(d, J, N, _np_ptr(x), _np_ptr(mu), _np_ptr(hw), _np_ptr(K), _np_ptr(sizes), *nul),
+           "rfm_plan")
+    nnz_rows, nnz, ncols, nrsq, max_rows, max_cols = (int(v) for v in sizes)
+    h = dict(row_off=np.zeros(J + 1, np.int64), rows=np.zeros(max(nnz_rows, 1), np.int32),
+             inc_blk=np.zeros(max(nnz_rows, 1), np.int32), rinc_off=np.zeros(N + 1, np.int64),
+             rinc=np.zeros(max(nnz_rows, 1), np.int64), feat_off=np.zeros(J + 1, np.int64),
+             blk_off=np.zeros(J + 1, np.int64), rsq_off=np.zeros(J + 1, np.int64))
+    _check(_lib.rfm_plan(d, J, N, _np_ptr(x), _np_ptr(mu), _np_ptr(hw), _np_ptr(K), _np_ptr(sizes),
+                         _np_ptr(h["row_off"]), _np_ptr(h["rows"]), _np_ptr(h["inc_blk"]),
+                         _np_ptr(h["rinc_off"]), _np_ptr(h["rinc"]), _np_ptr(h["feat_off"]),
+                         _np_ptr(h["blk_off"]), _np_ptr(h["rsq_off"])), "rfm_plan")
+    dev = {k: torch.from_numpy(v).to(device) for k, v in h.items()} if device is not None else {}
+    L = Layout(d=d, J=J, N=N, nnz_rows=nnz_rows, nnz=nnz, ncols=ncols, nrsq=nrsq, max_rows=max_rows,
+               max_cols=max_cols)
+    for k in ("row_off", "rows", "inc_blk", "rinc_off", "rinc", "feat_off", "blk_off", "rsq_off"):
+        setattr(L, k, dev[k].data_ptr() if dev else 0)
+    return Plan(L, h, dev)
+
+
+def problem_tensors(inst, device="cuda") -> dict:
+    """Device copies of an instance's per-row and per-feature arrays (marshalling only)."""
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+    return dict(x=t(inst.x, torch.float64), rowop=t(inst.rowop, torch.int32),
+                weight=t(inst.weight, torch.float64), rhs=t(inst.rhs, torch.float64),
+                mu=t(inst.mu, torch.float64), hw=t(inst.hw, torch.float64),
+                w=t(inst.w, torch.float64), b=t(inst.b, torch.float64),
+                kappa=float(inst.kappa), ksq=float(inst.ksq))
+
+
+def plan_instance(inst, device="cuda") -> Plan:
+    return rfm_plan(inst.d, inst.J, inst.x, inst.mu, inst.hw, np.diff(inst.feat_off), device)
+
+
+def rfm_assemble(plan: Plan, prob: dict, M=None, h=None):
+    L = plan.layout
+    dev = prob["x"].device
+    M = torch.empty(max(L.nnz, 1), dtype=torch.float64, device=dev) if M is None else M
+    h = torch.empty(L.N, dtype=torch.float64, device=dev) if h is None else h
+    P = Problem(x=prob["x"].data_ptr(), rowop=prob["rowop"].data_ptr(), weight=prob["weight"].data_ptr(),
+                rhs=prob["rhs"].data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(),
+                w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"])
+    nb = _lib.rfm_assemble_ws_bytes(C.byref(L))
+    ws = _ws(nb, dev)
+    _check(_lib.rfm_assemble(C.byref(L), C.byref(P), _ptr(M), _ptr(h), _ptr(ws), nb, _stream()),
+           "rfm_assemble")
+    return M, h
+
+
+def rfm_rrqr_filter(plan: Plan, M, tau, with_ratios=True, out=None):
+    L = plan.layout
+    dev = M.device
+    if out is None:
+        out = dict(rank=torch.empty(L.J, dtype=torch.int32, device=dev),
+                   kept=torch.empty(max(L.ncols, 1), dtype=torch.int32, device=dev),
+                   R=torch.zeros(max(L.nrsq, 1), dtype=torch.float64, device=dev),
+                   Q=torch.empty(max(L.nnz, 1), dtype=torch.float64, device=dev),
+                   ratios=torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if with_ratios else None)
+    nb = _lib.rfm_rrqr_ws_bytes(C.byref(L))
+    ws = _ws(nb, dev)
+    _check(_lib.rfm_rrqr_filter(C.byref(L), _ptr(M), float(tau), _ptr(out["rank"]), _ptr(out["kept"]),
+                                _ptr(out["R"]), _ptr(out["Q"]), _ptr(out["ratios"]), _ptr(ws), nb,
+                                _stream()), "rfm_rrqr_filter")
+    return out
+
+
+def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, maxit=10000,
+                   check_every=16, use_graph=0, form=FORM_Q, y=None, ws=None, times=None):
+    L = plan.layout
+    dev = h.device
+    y = torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if y is None else y
+    op = Operator(form=form, rank=fact["rank"].data_ptr(), Q=fact["Q"].data_ptr(),
+                  M=fact["M"].data_ptr() if fact.get("M") is not None else 0,
+                  kept=fact["kept"].data_ptr(), R=fact["R"].data_ptr())
+    opts = LsqrOpts(atol=atol, btol=btol, maxit=maxit, check_every=check_every, use_graph=use_graph,
+                    times=C.pointer(times) if times is not None else None)
+    info = LsqrInfo()
+    nb = _lib.rfm_lsqr_ws_bytes(C.byref(L))
+    if ws is None or ws.numel() < nb:
+        ws = _ws(nb, dev)
+    st = _check(_lib.rfm_lsqr_solve(C.byref(L), C.byref(op), _ptr(h), _ptr(y0), C.byref(opts), _ptr(y),
+                                    C.byref(info), _ptr(ws), nb, _stream()), "rfm_lsqr_solve",
+                allow=(RFM_ENOTCONV,))
+    return y, info
+
+
+def rfm_coefficients(plan: Plan, fact: dict, y, a=None):
+    L = plan.layout
+    a = torch.empty(max(L.ncols, 1), dtype=torch.float64, device=y.device) if a is None else a
+    _check(_lib.rfm_coefficients(C.byref(L), _ptr(fact["rank"]), _ptr(fact["kept"]), _ptr(fact["R"]),
+                                 _ptr(y), _ptr(a), _stream()), "rfm_coefficients")
+    return a

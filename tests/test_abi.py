@@ -1,0 +1,117 @@
+"""C-ABI checks that run without a GPU: the library loads, exports every function
+declared in include/rfm.h, plans supports exactly as the oracle defines them, and
+rejects invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import assembly
+from paper_2506_17626_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2506_17626_amd", "_lib", "librfm.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="librfm.so not built")
+
+
+def _declared():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(rfm_[a-z_0-9]+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = C.CDLL(LIB)
+    names = _declared()
+    assert {"rfm_plan", "rfm_assemble", "rfm_rrqr_filter", "rfm_lsqr_solve", "rfm_coefficients"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2506_17626_amd import rfm
+    assert set(names) <= set(rfm.EXPORTED)
+
+
+@pytest.mark.parametrize("name", ["poisson1d", "poisson2d", "heat3d", "helmholtz2d_uneven"])
+def test_plan_matches_oracle_supports_bitwise(name):
+    from paper_2506_17626_amd import rfm
+    inst = I.tiny(name)
+    plan = rfm.plan_instance(inst, device=None)
+    h = plan.host
+    rows = assembly.incidence(inst)
+    K = np.diff(inst.feat_off)
+    for j in range(inst.J):
+        got = h["rows"][h["row_off"][j]:h["row_off"][j + 1]]
+        assert np.array_equal(got, rows[j])
+        assert np.all(h["inc_blk"][h["row_off"][j]:h["row_off"][j + 1]] == j)
+    assert np.array_equal(h["feat_off"], inst.feat_off)
+    assert np.array_equal(np.diff(h["blk_off"]), np.array([len(r) for r in rows]) * K)
+    assert np.array_equal(np.diff(h["rsq_off"]), K * K)
+    # transpose: each row lists its incidences in ascending subdomain order
+    for r in range(0, inst.N, max(1, inst.N // 200)):
+        inc = h["rinc"][h["rinc_off"][r]:h["rinc_off"][r + 1]]
+        blks = h["inc_blk"][inc]
+        assert np.all(np.diff(blks) > 0)
+        assert np.all(h["rows"][inc] == r)
+        assert set(blks) == {j for j in range(inst.J) if r in set(rows[j])}
+    L = plan.layout
+    assert L.nnz_rows == sum(len(r) for r in rows)
+    assert L.max_rows == max(len(r) for r in rows) and L.max_cols == K.max()
+
+
+def test_plan_full_size_2d_and_support_edges_3d():
+    from paper_2506_17626_amd import rfm
+    inst = I.workload("poisson2d")
+    plan = rfm.plan_instance(inst, device=None)
+    rows = assembly.incidence(inst)
+    h = plan.host
+    for j in (0, 17, 128, 255):
+        assert np.array_equal(h["rows"][h["row_off"][j]:h["row_off"][j + 1]], rows[j])
+    assert plan.layout.nnz_rows == sum(len(r) for r in rows)
+    # the 3D grid puts points exactly on support edges; the strict binary64 test decides
+    inst = I.heat3d(S=4, K=8, n=12, nb=8)
+    plan = rfm.plan_instance(inst, device=None)
+    rows = assembly.incidence(inst)
+    for j in range(inst.J):
+        assert np.array_equal(plan.host["rows"][plan.host["row_off"][j]:plan.host["row_off"][j + 1]], rows[j])
+
+
+def test_invalid_arguments_rejected_without_device_work():
+    from paper_2506_17626_amd import rfm
+    lib = rfm._lib
+    assert lib.rfm_assemble(None, None, None, None, None, 0, None) == rfm.RFM_EINVAL
+    assert b"null layout" in lib.rfm_last_error()
+    inst = I.tiny("poisson1d")
+    plan = rfm.plan_instance(inst, device=None)
+    L = plan.layout
+    # tau outside [0,1)
+    assert lib.rfm_rrqr_filter(C.byref(L), None, 1.5, None, None, None, None, None, None, 0, None) == rfm.RFM_EINVAL
+    # layout arrays are required
+    assert lib.rfm_rrqr_filter(C.byref(L), None, 1e-8, None, None, None, None, None, None, 0, None) == rfm.RFM_EINVAL
+    opts = rfm.LsqrOpts(atol=1e-8, btol=1e-8, maxit=0, check_every=1)
+    info = rfm.LsqrInfo()
+    op = rfm.Operator(form=0)
+    assert lib.rfm_lsqr_solve(C.byref(L), C.byref(op), None, None, C.byref(opts), None, C.byref(info),
+                              None, 0, None) == rfm.RFM_EINVAL
+    # planning rejects bad geometry
+    x = np.zeros((3, 1))
+    mu = np.zeros((1, 1))
+    hw = np.zeros((1, 1))
+    K = np.ones(1, np.int32)
+    sizes = np.zeros(6, np.int64)
+    st = lib.rfm_plan(1, 1, 3, x.ctypes.data_as(C.c_void_p), mu.ctypes.data_as(C.c_void_p),
+                      hw.ctypes.data_as(C.c_void_p), K.ctypes.data_as(C.c_void_p),
+                      sizes.ctypes.data_as(C.c_void_p), *([None] * 8))
+    assert st == rfm.RFM_EINVAL
+
+
+def test_workspace_queries_scale_with_layout():
+    from paper_2506_17626_amd import rfm
+    small = rfm.plan_instance(I.tiny("poisson2d"), device=None).layout
+    big = rfm.plan_instance(I.poisson2d(S=6, K=40, n=7, nb=30), device=None).layout
+    for f in (rfm._lib.rfm_assemble_ws_bytes, rfm._lib.rfm_lsqr_ws_bytes):
+        assert 0 < f(C.byref(small)) < f(C.byref(big))

@@ -168,3 +168,22 @@ def test_incidence_strict_support_and_cover_bound():
     for r in rows:
         cover[r] += 1
     assert cover.max() <= 2 ** inst.d     # overlap fraction < 1/2
+
+
+@pytest.mark.parametrize("name", ["poisson1d", "heat3d", "helmholtz2d_uneven"])
+def test_entry_error_scale_bounds_binary64_rounding(name):
+    """The binary64 assembly sits within a few u * E of an extended-precision evaluation,
+    E the absolute-value evaluation used to size the GPU/oracle tolerance."""
+    inst = I.tiny(name)
+    rows, blocks, _ = assembly.assemble(inst)
+    ext = I.tiny(name)
+    for k in ("x", "mu", "hw", "w", "b", "weight", "rhs"):
+        setattr(ext, k, getattr(inst, k).astype(np.longdouble))
+    _, blocks_ext, _ = assembly.assemble(ext)
+    u = np.finfo(np.float64).eps / 2
+    worst = 0.0
+    for j in range(inst.J):
+        E = assembly.entry_error_scale(inst, rows, j)
+        err = np.abs(blocks[j] - blocks_ext[j].astype(np.float64))
+        worst = max(worst, float((err / (u * E)).max()))
+    assert worst < 4.0
