@@ -55,6 +55,24 @@ def fwd_bytes(m, r):
     return float(np.sum(8 * m * r + 8 * r + 8 * m))
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if the LSQR kernel source has
+    not changed since the counters were taken (else None)."""
+    import hashlib
+    import re
+    prof = os.path.join(ROOT, "profiles", "lsqr_qform_poisson2d_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2506_17626_amd", "csrc", "lsqr.hip")
+    if not os.path.exists(prof):
+        return None
+    txt = open(prof).read()
+    m = re.search(r"source hash at measurement: ([0-9a-f]+)", txt)
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if not m or m.group(1) != cur:
+        return None
+    row = re.search(r"\| " + re.escape(kernel) + r"<double> \| [^|]+\| [^|]+\| ([0-9.,]+) \|", txt)
+    return float(row.group(1).replace(",", "")) * 1e6 if row else None
+
+
 def cpu_baseline(inst, tau, nblocks):
     """The oracle's RRQR filter timed on the host on a bounded sample of the blocks."""
     from threadpoolctl import threadpool_limits
@@ -88,16 +106,20 @@ def cpu_baseline(inst, tau, nblocks):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson2d", choices=sorted(WORKLOAD_DESC))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tau", type=float, default=1e-12)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--maxit", type=int, default=20000)
-    ap.add_argument("--check-every", type=int, default=32)
+    ap.add_argument("--maxit", type=int, default=200000)
+    ap.add_argument("--check-every", type=int, default=64)
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-blocks", type=int, default=64)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this size once (a device copy of known "
+                         "size, used to calibrate the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the kernels are measured on one GPU's share of the "
@@ -137,7 +159,8 @@ def main():
         rfm.rfm_rrqr_filter(plan, M, args.tau, out=fact)
         ev[2].record()
         _, info = rfm.rfm_lsqr_solve(plan, fact, h, atol=args.tol, btol=args.tol, maxit=args.maxit,
-                                     check_every=args.check_every, y=y, ws=ws, times=kt)
+                                     check_every=args.check_every, use_graph=0 if args.no_graph else 1,
+                                     y=y, ws=ws, times=kt)
         ev[3].record()
         rfm.rfm_coefficients(plan, fact, y, a)
         ev[4].record()
@@ -156,31 +179,37 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
     phase_ms = {p: float(np.mean([r[0][k].elapsed_time(r[0][k + 1]) for r in recs])) for k, p in enumerate(phases)}
-    kern = {n: dict(ms=float(np.mean([r[1].ms[k] for r in recs])),
-                    launches=float(np.mean([r[1].launches[k] for r in recs])))
-            for k, n in enumerate(rfm.KernelTimes.NAMES)}
+    # sampled per-stage device times (HIP events inside the timed solves)
+    kern = {}
+    for k, nme in enumerate(rfm.KernelTimes.NAMES):
+        ms = float(np.sum([r[1].ms[k] for r in recs]))
+        cnt = float(np.sum([r[1].launches[k] for r in recs]))
+        kern[nme] = dict(avg_us=1e3 * ms / max(cnt, 1.0), sampled_launches=int(cnt))
     info = recs[-1][2]
+    iters = int(info.iters)
     ranks = fact["rank"].cpu().numpy().astype(np.int64)
     m = np.diff(plan.host["row_off"])
     n = np.diff(plan.host["feat_off"])
 
     # dominant kernel: the one with the most device time per step
-    per_step = {"rrqr_block": phase_ms["rrqr"], "adj_local": kern["adj_local"]["ms"],
-                "fwd_local": kern["fwd_local"]["ms"]}
+    per_step = {"rrqr_block": phase_ms["rrqr"],
+                "adj_local": kern["adj_local"]["avg_us"] * 1e-3 * iters,
+                "fwd_local": kern["fwd_local"]["avg_us"] * 1e-3 * iters}
     dom = max(per_step, key=per_step.get)
     if dom == "rrqr_block":
         flops = rrqr_flops(m, n, ranks)
         achieved = flops / (phase_ms["rrqr"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                "algorithmic_per_launch": flops}
+                "algorithmic_per_launch": flops, "avg_launch_us": phase_ms["rrqr"] * 1e3}
     else:
         per_launch = adj_bytes(m, ranks) if dom == "adj_local" else fwd_bytes(m, ranks)
-        avg_ms = kern[dom]["ms"] / max(kern[dom]["launches"], 1)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        avg_us = kern[dom]["avg_us"]
+        achieved = per_launch / (avg_us * 1e-6) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_per_launch": per_launch,
-                "avg_launch_us": avg_ms * 1e3}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom) if args.workload == "poisson2d"
+                and args.tau == 1e-12 else None, "algorithmic_per_launch": per_launch,
+                "avg_launch_us": avg_us}
 
     out = {
         "metric": METRIC,
@@ -192,15 +221,24 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOAD_DESC[args.workload], "name": args.workload, "J": inst.J,
                    "rows": int(L.N), "columns": int(L.ncols), "tau": args.tau, "seed": args.seed},
-        "lsqr": {"plain_fp64_ms": phase_ms["lsqr"], "iters": int(info.iters), "stop": int(info.stop),
+        "lsqr": {"plain_fp64_ms": phase_ms["lsqr"], "iters": iters, "stop": int(info.stop),
+                 "us_per_iter": 1e3 * phase_ms["lsqr"] / max(iters, 1),
                  "relres": info.relres, "eta": info.eta, "tol": args.tol,
                  "mixed_warm_ms": None},
-        "phase_ms": phase_ms, "lsqr_kernels": kern,
+        "phase_ms": phase_ms, "lsqr_stages": kern, "dominant_ms_per_step": per_step,
         "kept_columns": int(ranks.sum()),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.tau, args.cpu_blocks)
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nb
     print(json.dumps(out), flush=True)
 
 

@@ -157,11 +157,15 @@ typedef struct {
 } rfm_operator;
 
 /* Device time of the iteration kernels of one solve, measured with HIP events recorded
- * around every launch on the solve's stream (filled only when requested). */
+ * around each stage on the solve's stream.  Sampled: the first two iterations of every
+ * batch of check_every iterations are launched eagerly with events (the rest of the batch
+ * as usual, graph or eager); ms / launches is the average duration of a stage. */
 typedef struct {
-  double ms[4];           /* total ms of: forward block products, row gather, adjoint block
-                             products (+ rotation), y/w update (+ stop test) */
-  int64_t launches[4];    /* launches counted (iterations that ran, not the no-op tail) */
+  double ms[5];           /* total ms of the stages: [0] forward block products (R form: with
+                             the triangular solves), [1] row gather + beta, [2] adjoint block
+                             products (R form: with the transposed solves), [3] alpha and the
+                             rotation, [4] y/w update + stop test */
+  int64_t launches[5];    /* sampled launches counted (only iterations that did work) */
 } rfm_kernel_times;
 
 typedef struct {
@@ -169,7 +173,9 @@ typedef struct {
   int64_t maxit;          /* iteration limit (>= 1)                         */
   int32_t check_every;    /* iterations launched between host checks of the stop flag (>= 1) */
   int32_t use_graph;      /* 1: replay the per-check batch of launches as a HIP graph */
-  rfm_kernel_times *times;/* host, nullable: per-kernel device times of the iterations */
+  rfm_kernel_times *times;/* host, nullable: sampled per-stage device times (see above) */
+  double *history;        /* device, nullable, [2 * maxit]: per iteration the estimates of
+                             ||r|| and ||A^T r|| (entries past the last iteration untouched) */
 } rfm_lsqr_opts;
 
 typedef struct {

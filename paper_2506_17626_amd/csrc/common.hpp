@@ -55,38 +55,6 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
   return t;
 }
 
-// Agent-scope load that bypasses non-coherent caches (used to read partial results
-// written by other workgroups of the same launch).
-__device__ __forceinline__ double load_agent(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// "Last workgroup" test of a grid-wide reduction: every workgroup writes its partial,
-// then calls this; exactly one workgroup (the last to arrive) gets true and may read
-// all partials.  The counter is reset by the last workgroup, so it is ready for the
-// next launch without a memset.
-__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned nblocks, int *flag_lds) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    int last = (prev == nblocks - 1);
-    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *flag_lds = last;
-  }
-  __syncthreads();
-  const bool last = *flag_lds != 0;
-  if (last) __threadfence();
-  return last;
-}
-
-// Deterministic sum of n partials by one workgroup (fixed assignment and tree).
-__device__ __forceinline__ double sum_partials(const double *part, int64_t n, double *scratch) {
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += load_agent(part + i);
-  return block_sum(s, scratch);
-}
-
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace rfm

@@ -4,19 +4,22 @@
 // Operator A = sum_j V_j^T Q_hat_j W_hat_j (Q form).  Vectors over columns use the
 // padded per-feature layout (entry (j,k) at feat_off[j] + k, k < r_j; the rest stay 0).
 //
-// One LSQR iteration = four launches on the caller's stream:
+// One LSQR iteration = four data-parallel launches, each followed by a one-workgroup
+// reduction, on the caller's stream:
 //   fwd_local   t_(j,i) = sum_k Q_hat_j[i,k] v_j[k]       lane <-> row, coalesced column reads
 //   fwd_gather  p_r = sum_{j covering r} t_(j,r) - alpha u_r, summed in ascending j (no
 //               atomics, so the result does not depend on scheduling); ||p||^2 partials
-//   adj_local   z_j = Q_hat_j^T (p / beta) restricted to I_j (rows gathered to LDS once per
-//               block), q = z - beta v; ||q||^2 partials; the last workgroup finishes the
-//               norm and does the Givens-rotation scalar step of Paige and Saunders
-//   yw_update   y += (phi/rho) w, w = v - (theta/rho) w; ||y||^2; the last workgroup
-//               applies the stopping rule and raises the done flag
-// Grid-wide norms are finished by the last workgroup to arrive (threadfence + counter),
-// summing the per-workgroup partials in a fixed order.  After the done flag is up every
-// kernel returns at once, so the host may launch iterations in batches and only reads
-// the scalar state between batches.
+//               -> reduce_step: beta
+//   adj_local   z_j = Q_hat_j^T (p / beta) over column tiles of I_j x r_j (rows gathered to
+//               LDS once per workgroup), q = z - beta v; ||q||^2 partials
+//               -> reduce_step: alpha and the Givens-rotation scalar step of Paige-Saunders
+//   yw_update   y += (phi/rho) w, w = v - (theta/rho) w; ||y||^2 partials
+//               -> reduce_step: ||y|| and the stopping rule (raises the done flag)
+// Every grid-wide sum is a fixed-order sum of per-workgroup partials finished by a single
+// workgroup, so results are bitwise reproducible, and only that workgroup writes the
+// scalar state.  After the done flag is up every kernel returns at once, so the host
+// launches iterations in batches (optionally one captured HIP graph per batch) and only
+// reads the scalar state between batches.
 #include <cmath>
 #include <vector>
 
@@ -34,22 +37,23 @@ struct State {
   double atol, btol;
   int64_t iter, maxit;
   int32_t done, stop;
+  double *history;         // nullable device [2 * maxit]: (rnorm, artnorm) estimates
 };
 
 enum Mode : int { ITER = 0, INIT = 1, RESID = 2, COPYH = 3 };
+enum Flags : int { F_CHECK_DONE = 1, F_DIV_ALPHA = 2, F_DIV_BETA = 4, F_COMBINE = 8 };
+enum Reduce : int { R_BETA = 0, R_BETA_INIT = 1, R_ALPHA = 2, R_ALPHA_INIT = 3, R_Y = 4, R_Y_INIT = 5,
+                    R_CHK_R = 6, R_CHK_AT = 7 };
 
 constexpr int kRowTile = 256;
-constexpr int kAdjThreads = 512;
+constexpr int kAdjThreads = 256;
 constexpr int kVecThreads = 256;
+constexpr int kRedThreads = 1024;
+constexpr int kStages = 5;   // timed stages of one iteration (see rfm_kernel_times)
 
 __global__ void fill_zero(double *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
-}
-
-__global__ void fill_zero_u32(unsigned *p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
 }
 
 // y <- y0 on kept coordinates (or 0), 0 elsewhere.
@@ -62,48 +66,75 @@ __global__ void init_y(rfm_layout L, const int32_t *rank, const double *y0, doub
   y[f0 + k] = (y0 && k < rank[j]) ? y0[f0 + k] : 0.0;
 }
 
-// t_(j,i) = sum_k Q_hat_j[i,k] * v_j[k], v = vin / alpha (ITER) or vin (otherwise).
-__global__ __launch_bounds__(kRowTile) void fwd_local(rfm_layout L, const double *__restrict__ Q,
+// Operand element types of the block products: binary64, binary32, and bfloat16 stored as
+// its upper 16 bits (products of the narrow types accumulate in binary32).
+struct bf16_t {
+  uint16_t bits;
+};
+template <typename T> struct Acc { using type = double; };
+template <> struct Acc<float> { using type = float; };
+template <> struct Acc<bf16_t> { using type = float; };
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ float widen(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+
+// Column k of block j's operand: Q_hat_j[:, k] (Q form, k < r_j), or the kept column
+// M_j[:, kept_k] (R form, KEPT = true).
+template <typename T, bool KEPT>
+__device__ __forceinline__ const T *operand_col(const T *Op, int64_t base, const int *kept_lds, int k, int m) {
+  return Op + base + (int64_t)(KEPT ? kept_lds[k] : k) * m;
+}
+
+// t_(j,i) = sum_k Op_j[i,k] * v_j[k] with v = vin / alpha (F_DIV_ALPHA) or vin.
+template <typename T, bool KEPT>
+__global__ __launch_bounds__(kRowTile) void fwd_local(rfm_layout L, const T *__restrict__ Op,
+                                                      const int32_t *__restrict__ kept,
                                                       const int32_t *__restrict__ rank,
                                                       const double *__restrict__ vin,
                                                       double *__restrict__ t, const State *st,
-                                                      int mode) {
-  extern __shared__ double vs[];
-  if (mode == ITER && st->done) return;
+                                                      int flags) {
+  using A = typename Acc<T>::type;
+  extern __shared__ double smem[];
+  if ((flags & F_CHECK_DONE) && st->done) return;
   const int j = blockIdx.y;
   const int64_t r0 = L.row_off[j];
   const int m = (int)(L.row_off[j + 1] - r0);
   if ((int)blockIdx.x * kRowTile >= m) return;
   const int64_t f0 = L.feat_off[j];
   const int r = rank[j];
-  const double alpha = (mode == ITER) ? st->alpha : 1.0;
-  for (int k = threadIdx.x; k < r; k += kRowTile) vs[k] = (mode == ITER) ? vin[f0 + k] / alpha : vin[f0 + k];
+  A *vs = (A *)smem;
+  int *ks = (int *)(smem + L.max_cols);
+  const double alpha = (flags & F_DIV_ALPHA) ? st->alpha : 1.0;
+  for (int k = threadIdx.x; k < r; k += kRowTile) {
+    vs[k] = (A)((flags & F_DIV_ALPHA) ? vin[f0 + k] / alpha : vin[f0 + k]);
+    if (KEPT) ks[k] = kept[f0 + k];
+  }
   __syncthreads();
   const int i = blockIdx.x * kRowTile + threadIdx.x;
   if (i >= m) return;
-  const double *__restrict__ q = Q + L.blk_off[j] + i;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  const int64_t base = L.blk_off[j] + i;
+  A acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
   int k = 0;
   for (; k + 4 <= r; k += 4) {
-    acc0 += q[(int64_t)k * m] * vs[k];
-    acc1 += q[(int64_t)(k + 1) * m] * vs[k + 1];
-    acc2 += q[(int64_t)(k + 2) * m] * vs[k + 2];
-    acc3 += q[(int64_t)(k + 3) * m] * vs[k + 3];
+    acc0 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k, m)) * vs[k];
+    acc1 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k + 1, m)) * vs[k + 1];
+    acc2 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k + 2, m)) * vs[k + 2];
+    acc3 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k + 3, m)) * vs[k + 3];
   }
-  for (; k < r; ++k) acc0 += q[(int64_t)k * m] * vs[k];
-  t[r0 + i] = (acc0 + acc1) + (acc2 + acc3);
+  for (; k < r; ++k) acc0 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k, m)) * vs[k];
+  t[r0 + i] = (double)((acc0 + acc1) + (acc2 + acc3));
 }
 
 // p_r = sum_j t_(j,r) - alpha * (pcur_r / beta)     (ITER)
 // p_r = h_r - sum_j t_(j,r)                         (RESID)
 // p_r = h_r                                         (COPYH)
+// Per-workgroup partial sums of p^2 (and of h^2 outside ITER) go to part[] / part2[].
 __global__ __launch_bounds__(kVecThreads) void fwd_gather(rfm_layout L, const double *__restrict__ t,
                                                           const double *__restrict__ h,
                                                           const double *__restrict__ pcur,
                                                           double *__restrict__ pnew, double *part,
-                                                          unsigned *counter, State *st, int mode) {
+                                                          double *part2, const State *st, int mode) {
   __shared__ double red[kVecThreads / kWave];
-  __shared__ int last_flag;
   if (mode == ITER && st->done) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double val = 0.0, hh = 0.0;
@@ -123,139 +154,233 @@ __global__ __launch_bounds__(kVecThreads) void fwd_gather(rfm_layout L, const do
     pnew[r] = val;
   }
   const double bs = block_sum(val * val, red);
-  const double bh = (mode == ITER) ? 0.0 : block_sum(hh, red);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = bs;
-    if (mode != ITER) part[gridDim.x + blockIdx.x] = bh;
-  }
-  if (!arrive_last(counter, gridDim.x, &last_flag)) return;
-  const double tot = sum_partials(part, gridDim.x, red);
-  const double toth = (mode == ITER) ? 0.0 : sum_partials(part + gridDim.x, gridDim.x, red);
-  if (threadIdx.x == 0) {
-    st->beta_next = sqrt(tot);
-    if (mode != ITER) st->hnorm = sqrt(toth);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+  if (mode != ITER) {
+    const double bh = block_sum(hh, red);
+    if (threadIdx.x == 0) part2[blockIdx.x] = bh;
   }
 }
 
-// z_j = Q_hat_j^T u_{I_j} with u = pnew / beta_next (ITER, INIT) or pnew (RESID);
-// q = z - beta_next * (qcur / alpha) (ITER), q = z (otherwise).  One workgroup per block.
-__global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const double *__restrict__ Q,
+// z_j = Op_j^T u_{I_j} over a tile of ct columns of block j, u = pnew / beta_next
+// (F_DIV_BETA) or pnew; with F_COMBINE q = z - beta_next * (qcur / alpha), else q = z.
+// Each wave takes 4 columns at a time; the block's residual rows are gathered to LDS once
+// per workgroup.  One partial of sum q^2 per workgroup.
+template <typename T, bool KEPT>
+__global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const T *__restrict__ Op,
+                                                         const int32_t *__restrict__ kept,
                                                          const int32_t *__restrict__ rank,
                                                          const double *__restrict__ pnew,
                                                          const double *__restrict__ qcur,
                                                          double *__restrict__ qnew, double *part,
-                                                         unsigned *counter, State *st, int mode) {
-  extern __shared__ double us[];
-  __shared__ double red[kAdjThreads / kWave];
+                                                         int ct, const State *st, int flags) {
+  using A = typename Acc<T>::type;
+  extern __shared__ double smem[];
   __shared__ double colsum[kAdjThreads / kWave];
-  __shared__ int last_flag;
-  if (mode == ITER && st->done) return;
-  const int j = blockIdx.x;
+  if ((flags & F_CHECK_DONE) && st->done) return;
+  constexpr int NW = kAdjThreads / kWave;
+  const int j = blockIdx.y;
+  const int r = rank[j];
+  const int k0 = blockIdx.x * ct;
+  const int64_t pidx = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  if (k0 >= r) {
+    if (threadIdx.x == 0) part[pidx] = 0.0;
+    return;
+  }
+  const int k1 = min(r, k0 + ct);
   const int64_t r0 = L.row_off[j];
   const int m = (int)(L.row_off[j + 1] - r0);
   const int64_t f0 = L.feat_off[j];
-  const int r = rank[j];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  constexpr int NW = kAdjThreads / kWave;
   const double bn = st->beta_next;
   const double alpha = st->alpha;
+  A *us = (A *)smem;
+  int *ks = (int *)(smem + L.max_rows);
+  for (int i = threadIdx.x; i < m; i += kAdjThreads) {
+    const double p = pnew[L.rows[r0 + i]];
+    us[i] = (A)((flags & F_DIV_BETA) ? (bn > 0.0 ? p / bn : 0.0) : p);
+  }
+  if (KEPT)
+    for (int k = k0 + threadIdx.x; k < k1; k += kAdjThreads) ks[k - k0] = kept[f0 + k];
+  __syncthreads();
+  const int64_t base = L.blk_off[j];
   double ssq = 0.0;
-  if (r > 0) {
-    for (int i = threadIdx.x; i < m; i += kAdjThreads) {
-      const double p = pnew[L.rows[r0 + i]];
-      us[i] = (mode == RESID) ? p : (bn > 0.0 ? p / bn : 0.0);
+  for (int k = k0 + 4 * wid; k < k1; k += 4 * NW) {
+    // column k of the tile: Q_hat_j[:, k], or M_j[:, kept_k] with kept_k staged at ks[k - k0]
+    auto col = [&](int kk) { return Op + base + (int64_t)(KEPT ? ks[kk - k0] : kk) * m; };
+    const T *__restrict__ c0 = col(k);
+    const T *__restrict__ c1 = col(min(k + 1, k1 - 1));
+    const T *__restrict__ c2 = col(min(k + 2, k1 - 1));
+    const T *__restrict__ c3 = col(min(k + 3, k1 - 1));
+    A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    A b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    int i = lane;
+    for (; i + kWave < m; i += 2 * kWave) {
+      const A u0 = us[i], u1 = us[i + kWave];
+      a0 += (A)widen(c0[i]) * u0;
+      a1 += (A)widen(c1[i]) * u0;
+      a2 += (A)widen(c2[i]) * u0;
+      a3 += (A)widen(c3[i]) * u0;
+      b0 += (A)widen(c0[i + kWave]) * u1;
+      b1 += (A)widen(c1[i + kWave]) * u1;
+      b2 += (A)widen(c2[i + kWave]) * u1;
+      b3 += (A)widen(c3[i + kWave]) * u1;
     }
-    __syncthreads();
-    const double *__restrict__ Qj = Q + L.blk_off[j];
-    for (int k = 2 * wid; k < r; k += 2 * NW) {
-      const bool two = (k + 1 < r);
-      const double *__restrict__ c0 = Qj + (int64_t)k * m;
-      const double *__restrict__ c1 = Qj + (int64_t)(two ? k + 1 : k) * m;
-      double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
-      int i = lane;
-      for (; i + kWave < m; i += 2 * kWave) {
-        const double u0 = us[i], u1 = us[i + kWave];
-        a0 += c0[i] * u0;
-        b0 += c1[i] * u0;
-        a1 += c0[i + kWave] * u1;
-        b1 += c1[i + kWave] * u1;
-      }
-      if (i < m) {
-        a0 += c0[i] * us[i];
-        b0 += c1[i] * us[i];
-      }
-      const double z0 = wave_sum(a0 + a1);
-      const double z1 = wave_sum(b0 + b1);
-      if (lane == 0) {
-        double q0 = z0, q1 = z1;
-        if (mode == ITER) {
-          q0 = z0 - bn * (qcur[f0 + k] / alpha);
-          if (two) q1 = z1 - bn * (qcur[f0 + k + 1] / alpha);
-        }
-        qnew[f0 + k] = q0;
-        ssq += q0 * q0;
-        if (two) {
-          qnew[f0 + k + 1] = q1;
-          ssq += q1 * q1;
-        }
-      }
+    if (i < m) {
+      const A u0 = us[i];
+      a0 += (A)widen(c0[i]) * u0;
+      a1 += (A)widen(c1[i]) * u0;
+      a2 += (A)widen(c2[i]) * u0;
+      a3 += (A)widen(c3[i]) * u0;
+    }
+    const double z[4] = {wave_sum((double)(a0 + b0)), wave_sum((double)(a1 + b1)),
+                         wave_sum((double)(a2 + b2)), wave_sum((double)(a3 + b3))};
+    if (lane < 4 && k + lane < k1) {
+      double zz = z[0];
+      if (lane == 1) zz = z[1];
+      if (lane == 2) zz = z[2];
+      if (lane == 3) zz = z[3];
+      const int kk = k + lane;
+      const double q = (flags & F_COMBINE) ? zz - bn * (qcur[f0 + kk] / alpha) : zz;
+      qnew[f0 + kk] = q;
+      ssq += q * q;
     }
   }
-  // per-workgroup partial (lane 0 of each wave holds its columns' sum of squares)
+  // lanes 0..3 hold the squares of their columns; sum them in lane order
+  ssq = wave_sum(ssq);
   if (lane == 0) colsum[wid] = ssq;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < NW; ++w) s += colsum[w];
-    part[blockIdx.x] = s;
+    part[pidx] = s;
   }
-  if (!arrive_last(counter, gridDim.x, &last_flag)) return;
-  const double tot = sum_partials(part, gridDim.x, red);
-  if (threadIdx.x != 0) return;
-  const double an = sqrt(tot);
-  if (mode == RESID) {
-    st->artnorm = an;
-    st->rnorm = st->beta_next;
-    return;
-  }
-  if (mode == INIT) {
-    st->alpha = an;
-    st->beta = bn;
-    st->rhobar = an;
-    st->phibar = bn;
-    st->rnorm = bn;
-    st->artnorm = an * bn;
-    st->iter = 0;
-    st->stop = 0;
-    st->done = (an == 0.0 || bn == 0.0) ? 1 : 0;
-    if (st->done) st->stop = 4;
-    return;
-  }
-  // Givens rotation eliminating beta_{i+1} (Paige-Saunders recurrences)
-  const double rho = hypot(st->rhobar, bn);
-  const double c = st->rhobar / rho;
-  const double s = bn / rho;
-  const double theta = s * an;
-  const double phi = c * st->phibar;
-  st->rhobar = -c * an;
-  st->phibar = s * st->phibar;
-  st->phi_rho = phi / rho;
-  st->theta_rho = theta / rho;
-  st->rnorm = st->phibar;
-  st->artnorm = st->phibar * an * fabs(c);
-  st->alpha = an;
-  st->beta = bn;
 }
 
-// ITER: y += (phi/rho) w ; w = v - (theta/rho) w with v = q / alpha; stop test.
-// INIT: w = q / alpha ; ||y||.
+// Blocked triangular solves with R_hat_j (upper, column-major in its K_j x K_j slot), one
+// workgroup per block.  Tiles of 64 unknowns: the diagonal tile is staged in LDS and solved
+// by one wave with shuffles (no barriers), the rest of the right-hand side is updated by the
+// whole workgroup with coalesced reads of R.
+constexpr int kTri = 64;
+constexpr int kTriThreads = 256;
+
+// x = R^{-1} b, b = vin / alpha (F_DIV_ALPHA) or vin; writes xout (entries k < r_j).
+__global__ __launch_bounds__(kTriThreads) void trsv_upper(rfm_layout L, const int32_t *__restrict__ rank,
+                                                          const double *__restrict__ R,
+                                                          const double *__restrict__ vin,
+                                                          double *__restrict__ xout, const State *st,
+                                                          int flags) {
+  extern __shared__ double smem[];
+  if ((flags & F_CHECK_DONE) && st->done) return;
+  const int j = blockIdx.x;
+  const int64_t f0 = L.feat_off[j];
+  const int n = (int)(L.feat_off[j + 1] - f0);
+  const int r = rank[j];
+  if (r == 0) return;
+  const double *__restrict__ Rj = R + L.rsq_off[j];
+  double *x = smem;
+  double *D = smem + L.max_cols;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const double alpha = (flags & F_DIV_ALPHA) ? st->alpha : 1.0;
+  for (int k = threadIdx.x; k < r; k += kTriThreads)
+    x[k] = (flags & F_DIV_ALPHA) ? vin[f0 + k] / alpha : vin[f0 + k];
+  for (int t = (r - 1) / kTri; t >= 0; --t) {
+    const int k0 = t * kTri, w = min(kTri, r - k0);
+    for (int e = threadIdx.x; e < kTri * kTri; e += kTriThreads) {
+      const int c = e / kTri, rr = e % kTri;
+      D[e] = (c < w && rr <= c) ? Rj[(int64_t)(k0 + c) * n + k0 + rr] : 0.0;
+    }
+    __syncthreads();
+    if (wid == 0) {
+      double xi = (lane < w) ? x[k0 + lane] : 0.0;
+      for (int c = w - 1; c >= 0; --c) {
+        if (lane == c) xi = xi / D[c * kTri + c];
+        const double xc = __shfl(xi, c, kWave);
+        if (lane < c) xi -= D[c * kTri + lane] * xc;
+      }
+      if (lane < w) x[k0 + lane] = xi;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k0; i += kTriThreads) {
+      double acc = 0.0;
+      for (int c = 0; c < w; ++c) acc += Rj[(int64_t)(k0 + c) * n + i] * x[k0 + c];
+      x[i] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < r; k += kTriThreads) xout[f0 + k] = x[k];
+}
+
+// w = R^{-T} z; with F_COMBINE q = w - beta_next * (qcur / alpha), else q = w; one partial
+// of sum q^2 per block.
+__global__ __launch_bounds__(kTriThreads) void trsv_upper_t(rfm_layout L, const int32_t *__restrict__ rank,
+                                                            const double *__restrict__ R,
+                                                            const double *__restrict__ z,
+                                                            const double *__restrict__ qcur,
+                                                            double *__restrict__ qnew, double *part,
+                                                            const State *st, int flags) {
+  extern __shared__ double smem[];
+  __shared__ double red[kTriThreads / kWave];
+  if ((flags & F_CHECK_DONE) && st->done) return;
+  const int j = blockIdx.x;
+  const int64_t f0 = L.feat_off[j];
+  const int n = (int)(L.feat_off[j + 1] - f0);
+  const int r = rank[j];
+  if (r == 0) {
+    if (threadIdx.x == 0) part[j] = 0.0;
+    return;
+  }
+  const double *__restrict__ Rj = R + L.rsq_off[j];
+  double *x = smem;
+  double *D = smem + L.max_cols;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  constexpr int NW = kTriThreads / kWave;
+  for (int k = threadIdx.x; k < r; k += kTriThreads) x[k] = z[f0 + k];
+  for (int t = 0; t * kTri < r; ++t) {
+    const int k0 = t * kTri, w = min(kTri, r - k0), k1 = k0 + w;
+    for (int e = threadIdx.x; e < kTri * kTri; e += kTriThreads) {
+      const int c = e / kTri, rr = e % kTri;
+      D[e] = (c < w && rr <= c) ? Rj[(int64_t)(k0 + c) * n + k0 + rr] : 0.0;
+    }
+    __syncthreads();
+    if (wid == 0) {
+      double xi = (lane < w) ? x[k0 + lane] : 0.0;
+      for (int c = 0; c < w; ++c) {
+        if (lane == c) xi = xi / D[c * kTri + c];
+        const double xc = __shfl(xi, c, kWave);
+        if (lane > c && lane < w) xi -= D[lane * kTri + c] * xc;
+      }
+      if (lane < w) x[k0 + lane] = xi;
+    }
+    __syncthreads();
+    // rows k1..r-1: x_i -= sum_{c in tile} R[k0+c, i] x_{k0+c}; column i of R is contiguous
+    for (int i = k1 + wid; i < r; i += NW) {
+      const double v = (lane < w) ? Rj[(int64_t)i * n + k0 + lane] * x[k0 + lane] : 0.0;
+      const double s = wave_sum(v);
+      if (lane == 0) x[i] -= s;
+    }
+    __syncthreads();
+  }
+  const double bn = st->beta_next, alpha = st->alpha;
+  double ssq = 0.0;
+  for (int k = threadIdx.x; k < r; k += kTriThreads) {
+    const double q = (flags & F_COMBINE) ? x[k] - bn * (qcur[f0 + k] / alpha) : x[k];
+    qnew[f0 + k] = q;
+    ssq += q * q;
+  }
+  ssq = block_sum(ssq, red);
+  if (threadIdx.x == 0) part[j] = ssq;
+}
+
+// ITER: y += (phi/rho) w ; w = v - (theta/rho) w with v = q / alpha.   INIT: w = q / alpha.
+// Per-workgroup partials of ||y||^2.
 __global__ __launch_bounds__(kVecThreads) void yw_update(int64_t n, const double *__restrict__ qnew,
                                                          double *__restrict__ w,
                                                          double *__restrict__ y, double *part,
-                                                         unsigned *counter, State *st, int mode) {
+                                                         const State *st, int mode) {
   __shared__ double red[kVecThreads / kWave];
-  __shared__ int last_flag;
   if (st->done && mode == ITER) return;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double a = st->alpha;
@@ -275,20 +400,93 @@ __global__ __launch_bounds__(kVecThreads) void yw_update(int64_t n, const double
   }
   const double bs = block_sum(yy, red);
   if (threadIdx.x == 0) part[blockIdx.x] = bs;
-  if (!arrive_last(counter, gridDim.x, &last_flag)) return;
-  const double tot = sum_partials(part, gridDim.x, red);
+}
+
+// One workgroup: finishes a grid-wide sum of partials in a fixed order and performs the
+// scalar step that needs it (the only writer of the state, so no other workgroup can
+// observe a half-updated state).
+__global__ __launch_bounds__(kRedThreads) void reduce_step(const double *part, int64_t n,
+                                                           const double *part2, State *st, int what) {
+  __shared__ double red[kRedThreads / kWave];
+  if ((what == R_BETA || what == R_ALPHA || what == R_Y) && st->done) return;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kRedThreads) s += part[i];
+  s = block_sum(s, red);
+  double s2 = 0.0;
+  if (what == R_BETA_INIT || what == R_CHK_R) {
+    double t = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kRedThreads) t += part2[i];
+    s2 = block_sum(t, red);
+  }
   if (threadIdx.x != 0) return;
-  st->ynorm = sqrt(tot);
-  if (mode != ITER) return;
-  st->iter += 1;
-  int stop = 0;
-  if (st->beta == 0.0 || st->alpha == 0.0) stop = 4;
-  else if (st->rnorm <= st->btol * st->hnorm + st->atol * st->anorm * st->ynorm) stop = 1;
-  else if (st->artnorm <= st->atol * st->anorm * st->rnorm) stop = 2;
-  else if (st->iter >= st->maxit) stop = 3;
-  if (stop) {
-    st->stop = stop;
-    st->done = 1;
+  switch (what) {
+    case R_BETA:
+      st->beta_next = sqrt(s);
+      break;
+    case R_BETA_INIT:
+      st->beta_next = sqrt(s);
+      st->hnorm = sqrt(s2);
+      break;
+    case R_ALPHA_INIT: {
+      const double an = sqrt(s), bn = st->beta_next;
+      st->alpha = an;
+      st->beta = bn;
+      st->rhobar = an;
+      st->phibar = bn;
+      st->rnorm = bn;
+      st->artnorm = an * bn;
+      st->iter = 0;
+      st->stop = 0;
+      st->done = (an == 0.0 || bn == 0.0) ? 1 : 0;
+      if (st->done) st->stop = 4;
+      break;
+    }
+    case R_ALPHA: {
+      // Givens rotation eliminating beta_{i+1} (Paige-Saunders recurrences)
+      const double an = sqrt(s), bn = st->beta_next;
+      const double rho = hypot(st->rhobar, bn);
+      const double c = st->rhobar / rho;
+      const double sn = bn / rho;
+      const double theta = sn * an;
+      const double phi = c * st->phibar;
+      st->rhobar = -c * an;
+      st->phibar = sn * st->phibar;
+      st->phi_rho = phi / rho;
+      st->theta_rho = theta / rho;
+      st->rnorm = st->phibar;
+      st->artnorm = st->phibar * an * fabs(c);
+      st->alpha = an;
+      st->beta = bn;
+      break;
+    }
+    case R_Y_INIT:
+      st->ynorm = sqrt(s);
+      break;
+    case R_Y: {
+      st->ynorm = sqrt(s);
+      st->iter += 1;
+      if (st->history && st->iter <= st->maxit) {
+        st->history[2 * (st->iter - 1)] = st->rnorm;
+        st->history[2 * (st->iter - 1) + 1] = st->artnorm;
+      }
+      int stop = 0;
+      if (st->beta == 0.0 || st->alpha == 0.0) stop = 4;
+      else if (st->rnorm <= st->btol * st->hnorm + st->atol * st->anorm * st->ynorm) stop = 1;
+      else if (st->artnorm <= st->atol * st->anorm * st->rnorm) stop = 2;
+      else if (st->iter >= st->maxit) stop = 3;
+      if (stop) {
+        st->stop = stop;
+        st->done = 1;
+      }
+      break;
+    }
+    case R_CHK_R:
+      st->rnorm = sqrt(s);
+      st->hnorm = sqrt(s2);
+      break;
+    case R_CHK_AT:
+      st->artnorm = sqrt(s);
+      break;
   }
 }
 
@@ -317,21 +515,34 @@ __global__ __launch_bounds__(256) void back_substitute(rfm_layout L, const int32
 }
 
 struct Work {
-  double *t, *p[2], *res, *q[2], *w, *z, *part;
+  double *t, *p[2], *res, *q[2], *w, *z, *xs, *zs, *part, *part2;
   State *st, *st2;
-  unsigned *counter;
   int64_t npart;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Column tile of the adjoint products: about 4096 workgroups in total, tiles a multiple
+// of 16 columns (4 waves x 4 columns).
+int adj_tile(const rfm_layout *L) {
+  const int64_t mc = L->max_cols > 0 ? L->max_cols : 1;
+  int64_t tiles = (4096 + L->J - 1) / L->J;
+  const int64_t max_tiles = (mc + 15) / 16;
+  if (tiles > max_tiles) tiles = max_tiles;
+  if (tiles < 1) tiles = 1;
+  const int64_t per = (mc + tiles - 1) / tiles;
+  return (int)(((per + 15) / 16) * 16);
+}
+
 size_t carve(const rfm_layout *L, char *base, Work *W) {
   const int64_t N = L->N, nc = L->ncols;
   const int64_t g_rows = (N + kVecThreads - 1) / kVecThreads;
   const int64_t g_cols = (nc + kVecThreads - 1) / kVecThreads;
-  int64_t npart = 2 * g_rows;
+  const int ct = adj_tile(L);
+  const int64_t g_adj = (int64_t)L->J * (((L->max_cols > 0 ? L->max_cols : 1) + ct - 1) / ct);
+  int64_t npart = g_rows;
   if (g_cols > npart) npart = g_cols;
-  if (L->J > npart) npart = L->J;
+  if (g_adj > npart) npart = g_adj;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     char *p = base ? base + off : nullptr;
@@ -347,10 +558,12 @@ size_t carve(const rfm_layout *L, char *base, Work *W) {
   w.q[1] = (double *)take(sizeof(double) * nc);
   w.w = (double *)take(sizeof(double) * nc);
   w.z = (double *)take(sizeof(double) * nc);
+  w.xs = (double *)take(sizeof(double) * nc);
+  w.zs = (double *)take(sizeof(double) * nc);
   w.part = (double *)take(sizeof(double) * npart);
+  w.part2 = (double *)take(sizeof(double) * npart);
   w.st = (State *)take(sizeof(State));
   w.st2 = (State *)take(sizeof(State));
-  w.counter = (unsigned *)take(sizeof(unsigned) * 64);
   w.npart = npart;
   if (W) *W = w;
   return off;
@@ -361,47 +574,86 @@ struct Launcher {
   const rfm_operator *A;
   const double *h;
   Work W;
-  hipStream_t st;
+  int ct;
+  bool rform;
 
-  size_t adj_lds() const { return sizeof(double) * (size_t)(L->max_rows > 0 ? L->max_rows : 1); }
-  size_t fwd_lds() const { return sizeof(double) * (size_t)(L->max_cols > 0 ? L->max_cols : 1); }
+  size_t fwd_lds() const { return (size_t)(L->max_cols > 0 ? L->max_cols : 1) * (sizeof(double) + sizeof(int)); }
+  size_t adj_lds() const {
+    return sizeof(double) * (size_t)(L->max_rows > 0 ? L->max_rows : 1) +
+           sizeof(int) * (size_t)(L->max_cols > 0 ? L->max_cols : 1);
+  }
+  size_t tri_lds() const { return sizeof(double) * ((size_t)(L->max_cols > 0 ? L->max_cols : 1) + kTri * kTri); }
+  unsigned g_rows() const { return ceil_div(L->N, kVecThreads); }
+  unsigned g_cols() const { return ceil_div(L->ncols, kVecThreads); }
+  unsigned g_adj_x() const { return ceil_div(L->max_cols > 0 ? L->max_cols : 1, ct); }
+  int64_t n_adj_part() const { return rform ? (int64_t)L->J : (int64_t)g_adj_x() * L->J; }
 
-  void fwd(const double *vin, State *s, int mode) {
-    if (L->max_rows > 0)
-      hipLaunchKernelGGL(fwd_local, dim3(ceil_div(L->max_rows, kRowTile), L->J), dim3(kRowTile),
-                         fwd_lds(), st, *L, A->Q, A->rank, vin, W.t, s, mode);
+  // t = A_local v (per-incidence block products); v = vin / alpha in ITER mode
+  void fwd(hipStream_t s, const double *vin, State *st, int mode) {
+    if (L->max_rows <= 0) return;
+    const int flags = (mode == ITER) ? (F_CHECK_DONE | F_DIV_ALPHA) : 0;
+    const dim3 grid(ceil_div(L->max_rows, kRowTile), L->J);
+    if (!rform) {
+      hipLaunchKernelGGL((fwd_local<double, false>), grid, dim3(kRowTile), fwd_lds(), s, *L, A->Q,
+                         (const int32_t *)nullptr, A->rank, vin, W.t, st, flags);
+    } else {
+      hipLaunchKernelGGL(trsv_upper, dim3(L->J), dim3(kTriThreads), tri_lds(), s, *L, A->rank, A->R, vin,
+                         W.xs, st, flags);
+      hipLaunchKernelGGL((fwd_local<double, true>), grid, dim3(kRowTile), fwd_lds(), s, *L, A->M, A->kept,
+                         A->rank, W.xs, W.t, st, flags & F_CHECK_DONE);
+    }
   }
-  void gather(const double *pcur, double *pnew, State *s, int mode) {
-    hipLaunchKernelGGL(fwd_gather, dim3(ceil_div(L->N, kVecThreads)), dim3(kVecThreads), 0, st, *L,
-                       W.t, h, pcur, pnew, W.part, W.counter, s, mode);
+  void gather(hipStream_t s, const double *pcur, double *pnew, State *st, int mode) {
+    hipLaunchKernelGGL(fwd_gather, dim3(g_rows()), dim3(kVecThreads), 0, s, *L, W.t, h, pcur, pnew,
+                       W.part, W.part2, st, mode);
   }
-  void adj(const double *pnew, const double *qcur, double *qnew, State *s, int mode) {
-    hipLaunchKernelGGL(adj_local, dim3(L->J), dim3(kAdjThreads), adj_lds(), st, *L, A->Q, A->rank,
-                       pnew, qcur, qnew, W.part, W.counter, s, mode);
+  // q = A^T u (- beta v in ITER mode), u = p / beta outside RESID mode; partials of ||q||^2
+  void adj(hipStream_t s, const double *pnew, const double *qcur, double *qnew, State *st, int mode) {
+    int flags = 0;
+    if (mode == ITER) flags = F_CHECK_DONE | F_DIV_BETA | F_COMBINE;
+    if (mode == INIT) flags = F_DIV_BETA;
+    const dim3 grid(g_adj_x(), L->J);
+    if (!rform) {
+      hipLaunchKernelGGL((adj_local<double, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->Q,
+                         (const int32_t *)nullptr, A->rank, pnew, qcur, qnew, W.part, ct, st, flags);
+    } else {
+      hipLaunchKernelGGL((adj_local<double, true>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->M, A->kept,
+                         A->rank, pnew, qcur, W.zs, W.part, ct, st, flags & ~F_COMBINE);
+      hipLaunchKernelGGL(trsv_upper_t, dim3(L->J), dim3(kTriThreads), tri_lds(), s, *L, A->rank, A->R, W.zs,
+                         qcur, qnew, W.part, st, flags & (F_CHECK_DONE | F_COMBINE));
+    }
   }
-  void yw(const double *qnew, double *y, State *s, int mode) {
-    hipLaunchKernelGGL(yw_update, dim3(ceil_div(L->ncols, kVecThreads)), dim3(kVecThreads), 0, st,
-                       L->ncols, qnew, W.w, y, W.part, W.counter, s, mode);
+  void yw(hipStream_t s, const double *qnew, double *y, State *st, int mode) {
+    hipLaunchKernelGGL(yw_update, dim3(g_cols()), dim3(kVecThreads), 0, s, L->ncols, qnew, W.w, y,
+                       W.part, st, mode);
   }
-  // ev (nullable): 5 events recorded around the four launches
-  void iteration(int64_t i, double *y, hipEvent_t *ev) {
+  void reduce(hipStream_t s, int64_t n, State *st, int what) {
+    hipLaunchKernelGGL(reduce_step, dim3(1), dim3(kRedThreads), 0, s, W.part, n, W.part2, st, what);
+  }
+  // ev (nullable): 6 events around the five stages of one iteration
+  void iteration(hipStream_t s, int64_t i, double *y, hipEvent_t *ev) {
     const int a = (int)((i - 1) & 1), b = (int)(i & 1);
-    if (ev) hipEventRecord(ev[0], st);
-    fwd(W.q[a], W.st, ITER);
-    if (ev) hipEventRecord(ev[1], st);
-    gather(W.p[a], W.p[b], W.st, ITER);
-    if (ev) hipEventRecord(ev[2], st);
-    adj(W.p[b], W.q[a], W.q[b], W.st, ITER);
-    if (ev) hipEventRecord(ev[3], st);
-    yw(W.q[b], y, W.st, ITER);
-    if (ev) hipEventRecord(ev[4], st);
+    if (ev) hipEventRecord(ev[0], s);
+    fwd(s, W.q[a], W.st, ITER);
+    if (ev) hipEventRecord(ev[1], s);
+    gather(s, W.p[a], W.p[b], W.st, ITER);
+    reduce(s, g_rows(), W.st, R_BETA);
+    if (ev) hipEventRecord(ev[2], s);
+    adj(s, W.p[b], W.q[a], W.q[b], W.st, ITER);
+    if (ev) hipEventRecord(ev[3], s);
+    reduce(s, n_adj_part(), W.st, R_ALPHA);
+    if (ev) hipEventRecord(ev[4], s);
+    yw(s, W.q[b], y, W.st, ITER);
+    reduce(s, g_cols(), W.st, R_Y);
+    if (ev) hipEventRecord(ev[5], s);
   }
 };
 
 struct EventPool {
   std::vector<hipEvent_t> ev;
   ~EventPool() {
-    for (hipEvent_t e : ev) hipEventDestroy(e);
+    for (hipEvent_t e : ev)
+      if (e) hipEventDestroy(e);
   }
   hipError_t init(size_t n) {
     ev.resize(n, nullptr);
@@ -410,6 +662,18 @@ struct EventPool {
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
+  }
+};
+
+// A batch of iterations captured once on a private stream and replayed on the caller's.
+struct Graph {
+  hipStream_t cap = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  ~Graph() {
+    if (ge) hipGraphExecDestroy(ge);
+    if (g) hipGraphDestroy(g);
+    if (cap) hipStreamDestroy(cap);
   }
 };
 
@@ -428,20 +692,24 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   rfm_status s0 = check_layout(L, "rfm_lsqr_solve");
   if (s0 != RFM_OK) return s0;
   if (!A || !A->rank || !opts || !h || !y || !info) return fail(RFM_EINVAL, "rfm_lsqr_solve: null pointer");
-  if (A->form != RFM_FORM_Q) return fail(RFM_EUNSUPPORTED, "rfm_lsqr_solve: only the Q form is built");
-  if (L->nnz > 0 && !A->Q) return fail(RFM_EINVAL, "rfm_lsqr_solve: null Q");
+  if (A->form != RFM_FORM_Q && A->form != RFM_FORM_R) return fail(RFM_EINVAL, "rfm_lsqr_solve: bad form");
+  if (A->form == RFM_FORM_Q && L->nnz > 0 && !A->Q) return fail(RFM_EINVAL, "rfm_lsqr_solve: null Q");
+  if (A->form == RFM_FORM_R && ((L->nnz > 0 && !A->M) || !A->kept || (L->nrsq > 0 && !A->R)))
+    return fail(RFM_EINVAL, "rfm_lsqr_solve: R form needs M, kept and R");
   if (opts->maxit < 1 || opts->check_every < 1 || !(opts->atol >= 0) || !(opts->btol >= 0))
     return fail(RFM_EINVAL, "rfm_lsqr_solve: bad options");
   if (ws_bytes < rfm_lsqr_ws_bytes(L) || !ws) return fail(RFM_EINVAL, "rfm_lsqr_solve: workspace too small");
-  if ((size_t)L->max_rows * sizeof(double) > 120 * 1024)
-    return fail(RFM_EUNSUPPORTED, "rfm_lsqr_solve: max_rows too large for LDS staging");
+  if ((size_t)L->max_rows * sizeof(double) + (size_t)L->max_cols * sizeof(int) > 120 * 1024 ||
+      ((size_t)L->max_cols + kTri * kTri) * sizeof(double) > 120 * 1024)
+    return fail(RFM_EUNSUPPORTED, "rfm_lsqr_solve: block too large for LDS staging");
   hipStream_t st = (hipStream_t)stream;
 
   Launcher X;
   X.L = L;
   X.A = A;
   X.h = h;
-  X.st = st;
+  X.ct = adj_tile(L);
+  X.rform = (A->form == RFM_FORM_R);
   carve(L, (char *)ws, &X.W);
 
   // ||A||_F = sqrt(sum_j r_j): the Q form has unit-norm columns
@@ -456,9 +724,9 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   hs.atol = opts->atol;
   hs.btol = opts->btol;
   hs.maxit = opts->maxit;
+  hs.history = opts->history;
   RFM_HIP_TRY(hipMemcpyAsync(X.W.st, &hs, sizeof(State), hipMemcpyHostToDevice, st));
   RFM_HIP_TRY(hipMemcpyAsync(X.W.st2, &hs, sizeof(State), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(fill_zero_u32, dim3(1), dim3(64), 0, st, X.W.counter, 64);
   for (double *b : {X.W.q[0], X.W.q[1], X.W.w, X.W.z})
     hipLaunchKernelGGL(fill_zero, dim3(ceil_div(L->ncols, 256)), dim3(256), 0, st, b, L->ncols);
   if (L->max_cols > 0)
@@ -467,47 +735,73 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
 
   // r0 = h - A y0, beta_1 u_1 = r0, alpha_1 v_1 = A^T u_1, w_1 = v_1
   if (y0) {
-    X.fwd(y, X.W.st, RESID);
-    X.gather(nullptr, X.W.p[0], X.W.st, RESID);
+    X.fwd(st, y, X.W.st, RESID);
+    X.gather(st, nullptr, X.W.p[0], X.W.st, RESID);
   } else {
-    X.gather(nullptr, X.W.p[0], X.W.st, COPYH);
+    X.gather(st, nullptr, X.W.p[0], X.W.st, COPYH);
   }
-  X.adj(X.W.p[0], nullptr, X.W.q[0], X.W.st, INIT);
-  X.yw(X.W.q[0], y, X.W.st, INIT);
+  X.reduce(st, X.g_rows(), X.W.st, R_BETA_INIT);
+  X.adj(st, X.W.p[0], nullptr, X.W.q[0], X.W.st, INIT);
+  X.reduce(st, X.n_adj_part(), X.W.st, R_ALPHA_INIT);
+  X.yw(st, X.W.q[0], y, X.W.st, INIT);
+  X.reduce(st, X.g_cols(), X.W.st, R_Y_INIT);
   RFM_LAUNCH_CHECK();
   RFM_HIP_TRY(hipMemcpyAsync(&hs, X.W.st, sizeof(State), hipMemcpyDeviceToHost, st));
   RFM_HIP_TRY(hipStreamSynchronize(st));
 
   int64_t i = 0;
-  const int64_t batch = opts->check_every;
+  // batches of an even number of iterations, so the ping-pong buffers return to their start;
+  // with timing requested the first two iterations of every batch are launched eagerly with
+  // events around each stage (a sample of the kernels' durations inside the same solve)
+  const int64_t batch = 2 * ((opts->check_every + 1) / 2);
+  const bool timed = opts->times != nullptr;
+  const int64_t sampled = timed ? 2 : 0;
+  const bool graph = opts->use_graph != 0 && batch > sampled;
   EventPool pool;
-  if (opts->times) {
+  Graph G;
+  if (timed) {
     *opts->times = rfm_kernel_times{};
-    RFM_HIP_TRY(pool.init((size_t)(5 * batch)));
+    RFM_HIP_TRY(pool.init((size_t)(kStages + 1) * sampled));
+  }
+  if (graph && !hs.done) {
+    RFM_HIP_TRY(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+    RFM_HIP_TRY(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+    for (int64_t b = sampled + 1; b <= batch; ++b) X.iteration(G.cap, b, y, nullptr);
+    hipError_t le = hipGetLastError();
+    hipError_t ce = hipStreamEndCapture(G.cap, &G.g);
+    if (le != hipSuccess) return fail(RFM_EHIP, std::string("capture launch: ") + hipGetErrorString(le));
+    if (ce != hipSuccess) return fail(RFM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    RFM_HIP_TRY(hipGraphInstantiate(&G.ge, G.g, nullptr, nullptr, 0));
   }
   while (!hs.done && i < opts->maxit) {
     const int64_t first = i + 1;
-    for (int64_t b = 0; b < batch; ++b)
-      X.iteration(++i, y, opts->times ? pool.ev.data() + 5 * b : nullptr);
+    for (int64_t b = 0; b < sampled; ++b) X.iteration(st, ++i, y, pool.ev.data() + (kStages + 1) * b);
+    if (graph) {
+      RFM_HIP_TRY(hipGraphLaunch(G.ge, st));
+      i += batch - sampled;
+    } else {
+      for (int64_t b = sampled; b < batch; ++b) X.iteration(st, ++i, y, nullptr);
+    }
     RFM_LAUNCH_CHECK();
     RFM_HIP_TRY(hipMemcpyAsync(&hs, X.W.st, sizeof(State), hipMemcpyDeviceToHost, st));
     RFM_HIP_TRY(hipStreamSynchronize(st));
-    if (opts->times) {
-      // iterations first..hs.iter did work; later launches of the batch returned at once
-      for (int64_t b = 0; b < batch && first + b <= hs.iter; ++b)
-        for (int k = 0; k < 4; ++k) {
-          float ms = 0.f;
-          RFM_HIP_TRY(hipEventElapsedTime(&ms, pool.ev[5 * b + k], pool.ev[5 * b + k + 1]));
-          opts->times->ms[k] += ms;
-          opts->times->launches[k] += 1;
-        }
-    }
+    // sampled iterations that did work (later launches return at once after the stop)
+    for (int64_t b = 0; b < sampled && first + b <= hs.iter; ++b)
+      for (int k = 0; k < kStages; ++k) {
+        float ms = 0.f;
+        const size_t e0 = (size_t)(kStages + 1) * b + k;
+        RFM_HIP_TRY(hipEventElapsedTime(&ms, pool.ev[e0], pool.ev[e0 + 1]));
+        opts->times->ms[k] += ms;
+        opts->times->launches[k] += 1;
+      }
   }
 
   // explicit residuals: r = h - A y, A^T r
-  X.fwd(y, X.W.st2, RESID);
-  X.gather(nullptr, X.W.res, X.W.st2, RESID);
-  X.adj(X.W.res, nullptr, X.W.z, X.W.st2, RESID);
+  X.fwd(st, y, X.W.st2, RESID);
+  X.gather(st, nullptr, X.W.res, X.W.st2, RESID);
+  X.reduce(st, X.g_rows(), X.W.st2, R_CHK_R);
+  X.adj(st, X.W.res, nullptr, X.W.z, X.W.st2, RESID);
+  X.reduce(st, X.n_adj_part(), X.W.st2, R_CHK_AT);
   RFM_LAUNCH_CHECK();
   State hc{};
   RFM_HIP_TRY(hipMemcpyAsync(&hc, X.W.st2, sizeof(State), hipMemcpyDeviceToHost, st));

@@ -46,8 +46,8 @@ class Operator(C.Structure):
 
 
 class KernelTimes(C.Structure):
-    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
-    NAMES = ("fwd_local", "fwd_gather", "adj_local", "yw_update")
+    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5)]
+    NAMES = ("fwd_local", "gather_beta", "adj_local", "alpha_rotation", "yw_update")
 
     def as_dict(self):
         return {n: dict(ms=self.ms[k], launches=self.launches[k]) for k, n in enumerate(self.NAMES)}
@@ -56,7 +56,7 @@ class KernelTimes(C.Structure):
 class LsqrOpts(C.Structure):
     _fields_ = [("atol", C.c_double), ("btol", C.c_double), ("maxit", C.c_int64),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("times", C.POINTER(KernelTimes))]
+                ("times", C.POINTER(KernelTimes)), ("history", _p)]
 
 
 class LsqrInfo(C.Structure):
@@ -210,7 +210,8 @@ def rfm_rrqr_filter(plan: Plan, M, tau, with_ratios=True, out=None):
 
 
 def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, maxit=10000,
-                   check_every=16, use_graph=0, form=FORM_Q, y=None, ws=None, times=None):
+                   check_every=16, use_graph=0, form=FORM_Q, y=None, ws=None, times=None,
+                   history=None):
     L = plan.layout
     dev = h.device
     y = torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if y is None else y
@@ -218,7 +219,7 @@ def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, max
                   M=fact["M"].data_ptr() if fact.get("M") is not None else 0,
                   kept=fact["kept"].data_ptr(), R=fact["R"].data_ptr())
     opts = LsqrOpts(atol=atol, btol=btol, maxit=maxit, check_every=check_every, use_graph=use_graph,
-                    times=C.pointer(times) if times is not None else None)
+                    times=C.pointer(times) if times is not None else None, history=_ptr(history))
     info = LsqrInfo()
     nb = _lib.rfm_lsqr_ws_bytes(C.byref(L))
     if ws is None or ws.numel() < nb:

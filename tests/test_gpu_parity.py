@@ -284,3 +284,64 @@ def test_end_to_end_gpu_pipeline(rfm, name):
     print(f"  iters gpu {info.iters} oracle {sol.info.iters}; eL1 gpu {e_gpu:.3e} oracle {e_or:.3e}", flush=True)
     assert info.stop in (1, 2)
     assert e_gpu <= 2 * e_or + 1e-6
+
+
+@pytest.mark.parametrize("name", ["poisson2d", "helmholtz2d_uneven"])
+def test_lsqr_graph_replay_matches_eager_bitwise(rfm, name):
+    """The iteration batch captured as a HIP graph and replayed many times (host sync
+    between replays) gives exactly the eager result; so does a second solve."""
+    inst = I.tiny(name)
+    print(f"[graph] {name}", flush=True)
+    rows, blocks, h = assembly.assemble(inst)
+    facts = rrqr.filter_blocks(blocks, 1e-10)
+    plan = rfm.plan_instance(inst)
+    K = np.diff(inst.feat_off)
+    fact = dict(rank=_dev(np.array([f.rank for f in facts]), torch.int32),
+                kept=_dev(H.pack_kept(plan.host, facts, K), torch.int32),
+                R=_dev(H.pack_r(plan.host, facts, K)), Q=_dev(H.pack_q(plan.host, facts, K)))
+    hd = _dev(h)
+    ye, ie = rfm.rfm_lsqr_solve(plan, fact, hd, atol=1e-10, btol=1e-10, maxit=300, check_every=4, use_graph=0)
+    for rep in range(2):
+        yg, ig = rfm.rfm_lsqr_solve(plan, fact, hd, atol=1e-10, btol=1e-10, maxit=300, check_every=4, use_graph=1)
+        torch.cuda.synchronize()
+        assert ig.iters == ie.iters and ig.stop == ie.stop
+        assert torch.equal(yg, ye), rep
+
+
+@pytest.mark.parametrize("name", ["poisson1d", "poisson2d", "heat3d", "helmholtz2d_uneven"])
+def test_lsqr_r_form_matches_oracle_r_form(rfm, name):
+    """R form (kept columns of M with blocked triangular solves) against the oracle's R form on
+    shared factors.  Tolerance: the a-posteriori cancellation level of the R form,
+    u * max_j ||M_hat_j|| ||R_hat_j^{-1}||, amplified by kappa(A), plus 1e-8."""
+    inst = I.tiny(name)
+    print(f"[rform] {name}", flush=True)
+    tau = 1e-8
+    rows, blocks, h = assembly.assemble(inst)
+    facts = rrqr.filter_blocks(blocks, tau)
+    plan = rfm.plan_instance(inst)
+    K = np.diff(inst.feat_off)
+    fact = dict(rank=_dev(np.array([f.rank for f in facts]), torch.int32),
+                kept=_dev(H.pack_kept(plan.host, facts, K), torch.int32),
+                R=_dev(H.pack_r(plan.host, facts, K)), Q=_dev(H.pack_q(plan.host, facts, K)),
+                M=_dev(H.pack_blocks(plan.host, blocks, K)))
+    Ar = olsqr.RForm(inst.N, rows, [b[:, f.kept] for b, f in zip(blocks, facts)], [f.R for f in facts])
+    Aq = olsqr.QForm(inst.N, rows, [f.Q for f in facts])
+    D = np.stack([Aq.matvec(e) for e in np.eye(Aq.n)], axis=1)
+    kappa = np.linalg.cond(D)
+    est = U * max(np.linalg.norm(b[:, f.kept], 2) * np.linalg.norm(np.linalg.inv(f.R), 2)
+                  for b, f in zip(blocks, facts) if f.rank)
+    tol = 100 * kappa * est + 1e-8
+    # fixed number of iterations: iterates of the same recurrence
+    y_or, _ = olsqr.lsqr(Ar, h, atol=0.0, btol=0.0, maxit=30)
+    y, info = rfm.rfm_lsqr_solve(plan, fact, _dev(h), atol=0.0, btol=0.0, maxit=30, form=rfm.FORM_R)
+    ypad = H.pack_y(inst.feat_off, facts, y_or)
+    rel = np.linalg.norm(y.cpu().numpy() - ypad) / np.linalg.norm(ypad)
+    print(f"  30 iterations: rel diff {rel:.2e} (tol {tol:.1e}, kappa {kappa:.1e}, est {est:.1e})", flush=True)
+    assert info.iters == 30 and rel <= tol
+    # converged: R form and Q form reach the same least-squares solution within the same level
+    y_or, info_or = olsqr.lsqr(Ar, h, atol=1e-12, btol=1e-12, maxit=20000)
+    y, info = rfm.rfm_lsqr_solve(plan, fact, _dev(h), atol=1e-12, btol=1e-12, maxit=20000, form=rfm.FORM_R)
+    ypad = H.pack_y(inst.feat_off, facts, y_or)
+    rel = np.linalg.norm(y.cpu().numpy() - ypad) / np.linalg.norm(ypad)
+    print(f"  converged: iters gpu {info.iters} oracle {info_or.iters}, rel diff {rel:.2e}", flush=True)
+    assert rel <= tol
