@@ -42,6 +42,14 @@ typedef enum {
   RFM_EUNSUPPORTED = 5    /* sizes beyond what the kernels are built for */
 } rfm_status;
 
+/* Element types of operand copies (the precision form). */
+typedef enum {
+  RFM_F64 = 0,            /* IEEE binary64                                           */
+  RFM_F32 = 1,            /* IEEE binary32, rounded to nearest even from binary64      */
+  RFM_BF16 = 2            /* bfloat16 (upper 16 bits of binary32), the binary32 value
+                             rounded to nearest even                                 */
+} rfm_dtype;
+
 /* Row operators (the linear PDE / boundary operators N and B_l of Section 2.1).
  * Inputs x have d coordinates; for RFM_OP_HEAT the last coordinate is time. */
 typedef enum {
@@ -154,7 +162,16 @@ typedef struct {
   const double *M;        /* device [nnz]  (RFM_FORM_R)                     */
   const int32_t *kept;    /* device [ncols] (RFM_FORM_R)                    */
   const double *R;        /* device [nrsq] (RFM_FORM_R)                     */
+  const void *Qlow;       /* device [nnz] elements of low_dtype, nullable: narrow copy of
+                             Q_hat from rfm_pack_q, used by the precision form */
+  int32_t low_dtype;      /* rfm_dtype of Qlow                              */
 } rfm_operator;
+
+/* Narrow copy of the explicit Q_hat for the precision form: the first r_j columns of every
+ * block rounded to binary32 or bfloat16 (rfm_dtype), written in the block layout of M with
+ * 4- or 2-byte elements.  Q device [nnz] binary64, Qlow device [nnz] of dtype. */
+rfm_status rfm_pack_q(const rfm_layout *L, const int32_t *rank, const double *Q, int32_t dtype,
+                      void *Qlow, void *stream);
 
 /* Device time of the iteration kernels of one solve, measured with HIP events recorded
  * around each stage on the solve's stream.  Sampled: the first two iterations of every
@@ -175,11 +192,21 @@ typedef struct {
   int32_t use_graph;      /* 1: replay the per-check batch of launches as a HIP graph */
   rfm_kernel_times *times;/* host, nullable: sampled per-stage device times (see above) */
   double *history;        /* device, nullable, [2 * maxit]: per iteration the estimates of
-                             ||r|| and ||A^T r|| (entries past the last iteration untouched) */
+                             ||r|| and ||A^T r|| (entries past the last iteration untouched;
+                             plain solves only) */
+  int32_t inner_dtype;    /* RFM_F64: plain LSQR.  RFM_F32 / RFM_BF16: precision form --
+                             binary64 residual refinement around LSQR on the narrow copy
+                             A->Qlow (products accumulated in binary32) */
+  int32_t max_outer;      /* precision form: refinement steps (>= 1)        */
+  int64_t max_inner;      /* precision form: iteration cap of one inner solve (>= 1) */
+  double inner_tol;       /* precision form: atol = btol of the inner solves, in (0, 1) */
 } rfm_lsqr_opts;
 
 typedef struct {
-  int64_t iters;          /* iterations performed                            */
+  int64_t iters;          /* iterations performed (precision form: inner iterations in total) */
+  int64_t outer;          /* precision form: refinement steps taken (0 for plain solves) */
+  int64_t polish;         /* precision form: binary64 LSQR iterations of the finish (included
+                             in iters)                                      */
   int32_t stop;           /* 1: S1, 2: S2, 3: maxit, 4: breakdown (exact solution) */
   double rnorm_est;       /* ||r|| estimate at the stop                      */
   double artnorm_est;     /* ||A^T r|| estimate at the stop                  */
@@ -200,6 +227,14 @@ size_t rfm_lsqr_ws_bytes(const rfm_layout *L);
  * on the recurrence estimates; breakdown (alpha or beta = 0) stops with the exact
  * solution.  After stopping the residuals are recomputed explicitly with the operator
  * and returned in info.
+ * Precision form (opts->inner_dtype != RFM_F64): y <- y0; repeat { r = h - A y and A^T r in
+ * binary64 with the full operator; stop by S1/S2 on these explicit values; solve
+ * min ||A_low d - r|| by LSQR with atol = btol = inner_tol (A_low the narrow Q_hat, binary32
+ * accumulation); y <- y + d } while ||A^T r|| at least halves per step (and for at most
+ * max_outer steps); then binary64 LSQR from y (the finish) until S1/S2.  Refinement through a
+ * narrow operator converges to A_low^T (h - A y) = 0, not A^T (h - A y) = 0, which on these
+ * least-squares systems (non-zero optimal residual) leaves ||A^T r|| near u_low ||A|| ||r||;
+ * the finish removes that bias.  opts->maxit caps all iterations together.
  * Vectors: h device [N]; y0, y device [ncols] (entry (j,k) for k < r_j at feat_off[j]+k
  * in pivot order; other entries of y are set to 0).  (sync): returns after the solve;
  * RFM_ENOTCONV if maxit was reached. */

@@ -514,8 +514,44 @@ __global__ __launch_bounds__(256) void back_substitute(rfm_layout L, const int32
   for (int k = threadIdx.x; k < r; k += blockDim.x) a[f0 + kept[f0 + k]] = x[k];
 }
 
+// Round the kept columns of Q_hat to binary32 (round to nearest even) or to bfloat16 (the
+// binary32 value rounded to nearest even on its upper 16 bits).
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+template <typename T> __device__ __forceinline__ T narrow(double v);
+template <> __device__ __forceinline__ float narrow<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ bf16_t narrow<bf16_t>(double v) { return bf16_t{bf16_bits((float)v)}; }
+
+template <typename T>
+__global__ __launch_bounds__(kRowTile) void pack_q(rfm_layout L, const int32_t *__restrict__ rank,
+                                                   const double *__restrict__ Q, T *__restrict__ out) {
+  const int j = blockIdx.y;
+  const int m = (int)(L.row_off[j + 1] - L.row_off[j]);
+  const int i = blockIdx.x * kRowTile + threadIdx.x;
+  if (i >= m) return;
+  const int r = rank[j];
+  const int64_t base = L.blk_off[j] + i;
+  for (int k = 0; k < r; ++k) out[base + (int64_t)k * m] = narrow<T>(Q[base + (int64_t)k * m]);
+}
+
+__global__ void axpy_inplace(int64_t n, const double *__restrict__ x, double *__restrict__ y) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) y[k] += x[k];
+}
+
+__global__ __launch_bounds__(kVecThreads) void sq_partials(int64_t n, const double *__restrict__ x, double *part) {
+  __shared__ double red[kVecThreads / kWave];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double v = (k < n) ? x[k] : 0.0;
+  const double bs = block_sum(v * v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
 struct Work {
-  double *t, *p[2], *res, *q[2], *w, *z, *xs, *zs, *part, *part2;
+  double *t, *p[2], *res, *q[2], *w, *z, *xs, *zs, *dy, *part, *part2;
   State *st, *st2;
   int64_t npart;
 };
@@ -560,6 +596,7 @@ size_t carve(const rfm_layout *L, char *base, Work *W) {
   w.z = (double *)take(sizeof(double) * nc);
   w.xs = (double *)take(sizeof(double) * nc);
   w.zs = (double *)take(sizeof(double) * nc);
+  w.dy = (double *)take(sizeof(double) * nc);
   w.part = (double *)take(sizeof(double) * npart);
   w.part2 = (double *)take(sizeof(double) * npart);
   w.st = (State *)take(sizeof(State));
@@ -576,6 +613,8 @@ struct Launcher {
   Work W;
   int ct;
   bool rform;
+  int dtype = RFM_F64;         // operand of the Q form: RFM_F64 (A->Q) or a narrow copy
+  const void *Qlow = nullptr;  // RFM_F32 / RFM_BF16 copy of Q_hat in the block layout
 
   size_t fwd_lds() const { return (size_t)(L->max_cols > 0 ? L->max_cols : 1) * (sizeof(double) + sizeof(int)); }
   size_t adj_lds() const {
@@ -593,9 +632,16 @@ struct Launcher {
     if (L->max_rows <= 0) return;
     const int flags = (mode == ITER) ? (F_CHECK_DONE | F_DIV_ALPHA) : 0;
     const dim3 grid(ceil_div(L->max_rows, kRowTile), L->J);
-    if (!rform) {
+    const int32_t *nk = nullptr;
+    if (!rform && dtype == RFM_F32) {
+      hipLaunchKernelGGL((fwd_local<float, false>), grid, dim3(kRowTile), fwd_lds(), s, *L,
+                         (const float *)Qlow, nk, A->rank, vin, W.t, st, flags);
+    } else if (!rform && dtype == RFM_BF16) {
+      hipLaunchKernelGGL((fwd_local<bf16_t, false>), grid, dim3(kRowTile), fwd_lds(), s, *L,
+                         (const bf16_t *)Qlow, nk, A->rank, vin, W.t, st, flags);
+    } else if (!rform) {
       hipLaunchKernelGGL((fwd_local<double, false>), grid, dim3(kRowTile), fwd_lds(), s, *L, A->Q,
-                         (const int32_t *)nullptr, A->rank, vin, W.t, st, flags);
+                         nk, A->rank, vin, W.t, st, flags);
     } else {
       hipLaunchKernelGGL(trsv_upper, dim3(L->J), dim3(kTriThreads), tri_lds(), s, *L, A->rank, A->R, vin,
                          W.xs, st, flags);
@@ -613,9 +659,16 @@ struct Launcher {
     if (mode == ITER) flags = F_CHECK_DONE | F_DIV_BETA | F_COMBINE;
     if (mode == INIT) flags = F_DIV_BETA;
     const dim3 grid(g_adj_x(), L->J);
-    if (!rform) {
+    const int32_t *nk = nullptr;
+    if (!rform && dtype == RFM_F32) {
+      hipLaunchKernelGGL((adj_local<float, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
+                         (const float *)Qlow, nk, A->rank, pnew, qcur, qnew, W.part, ct, st, flags);
+    } else if (!rform && dtype == RFM_BF16) {
+      hipLaunchKernelGGL((adj_local<bf16_t, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
+                         (const bf16_t *)Qlow, nk, A->rank, pnew, qcur, qnew, W.part, ct, st, flags);
+    } else if (!rform) {
       hipLaunchKernelGGL((adj_local<double, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->Q,
-                         (const int32_t *)nullptr, A->rank, pnew, qcur, qnew, W.part, ct, st, flags);
+                         nk, A->rank, pnew, qcur, qnew, W.part, ct, st, flags);
     } else {
       hipLaunchKernelGGL((adj_local<double, true>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->M, A->kept,
                          A->rank, pnew, qcur, W.zs, W.part, ct, st, flags & ~F_COMBINE);
@@ -677,60 +730,23 @@ struct Graph {
   }
 };
 
-}  // namespace
-}  // namespace rfm
-
-extern "C" size_t rfm_lsqr_ws_bytes(const rfm_layout *L) {
-  if (!L) return 0;
-  return rfm::carve(L, nullptr, nullptr);
-}
-
-extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A, const double *h,
-                                     const double *y0, const rfm_lsqr_opts *opts, double *y,
-                                     rfm_lsqr_info *info, void *ws, size_t ws_bytes, void *stream) {
-  using namespace rfm;
-  rfm_status s0 = check_layout(L, "rfm_lsqr_solve");
-  if (s0 != RFM_OK) return s0;
-  if (!A || !A->rank || !opts || !h || !y || !info) return fail(RFM_EINVAL, "rfm_lsqr_solve: null pointer");
-  if (A->form != RFM_FORM_Q && A->form != RFM_FORM_R) return fail(RFM_EINVAL, "rfm_lsqr_solve: bad form");
-  if (A->form == RFM_FORM_Q && L->nnz > 0 && !A->Q) return fail(RFM_EINVAL, "rfm_lsqr_solve: null Q");
-  if (A->form == RFM_FORM_R && ((L->nnz > 0 && !A->M) || !A->kept || (L->nrsq > 0 && !A->R)))
-    return fail(RFM_EINVAL, "rfm_lsqr_solve: R form needs M, kept and R");
-  if (opts->maxit < 1 || opts->check_every < 1 || !(opts->atol >= 0) || !(opts->btol >= 0))
-    return fail(RFM_EINVAL, "rfm_lsqr_solve: bad options");
-  if (ws_bytes < rfm_lsqr_ws_bytes(L) || !ws) return fail(RFM_EINVAL, "rfm_lsqr_solve: workspace too small");
-  if ((size_t)L->max_rows * sizeof(double) + (size_t)L->max_cols * sizeof(int) > 120 * 1024 ||
-      ((size_t)L->max_cols + kTri * kTri) * sizeof(double) > 120 * 1024)
-    return fail(RFM_EUNSUPPORTED, "rfm_lsqr_solve: block too large for LDS staging");
-  hipStream_t st = (hipStream_t)stream;
-
-  Launcher X;
-  X.L = L;
-  X.A = A;
-  X.h = h;
-  X.ct = adj_tile(L);
-  X.rform = (A->form == RFM_FORM_R);
-  carve(L, (char *)ws, &X.W);
-
-  // ||A||_F = sqrt(sum_j r_j): the Q form has unit-norm columns
-  std::vector<int32_t> hrank(L->J);
-  RFM_HIP_TRY(hipMemcpyAsync(hrank.data(), A->rank, sizeof(int32_t) * L->J, hipMemcpyDeviceToHost, st));
-  RFM_HIP_TRY(hipStreamSynchronize(st));
-  double nr = 0.0;
-  for (int32_t j = 0; j < L->J; ++j) nr += hrank[j];
-
+// LSQR with the launcher's operator on the right-hand side X.h, from y0 (nullable) into y.
+// Fills *out with the final scalar state (iterations, stop reason, estimates).
+rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, double atol, double btol,
+                    int64_t maxit, int check_every, bool use_graph, rfm_kernel_times *times,
+                    double *history, hipStream_t st, State *out) {
+  const rfm_layout *L = X.L;
   State hs{};
-  hs.anorm = std::sqrt(nr);
-  hs.atol = opts->atol;
-  hs.btol = opts->btol;
-  hs.maxit = opts->maxit;
-  hs.history = opts->history;
+  hs.anorm = anorm;
+  hs.atol = atol;
+  hs.btol = btol;
+  hs.maxit = maxit;
+  hs.history = history;
   RFM_HIP_TRY(hipMemcpyAsync(X.W.st, &hs, sizeof(State), hipMemcpyHostToDevice, st));
-  RFM_HIP_TRY(hipMemcpyAsync(X.W.st2, &hs, sizeof(State), hipMemcpyHostToDevice, st));
-  for (double *b : {X.W.q[0], X.W.q[1], X.W.w, X.W.z})
+  for (double *b : {X.W.q[0], X.W.q[1], X.W.w})
     hipLaunchKernelGGL(fill_zero, dim3(ceil_div(L->ncols, 256)), dim3(256), 0, st, b, L->ncols);
   if (L->max_cols > 0)
-    hipLaunchKernelGGL(init_y, dim3(ceil_div(L->max_cols, 256), L->J), dim3(256), 0, st, *L, A->rank, y0, y);
+    hipLaunchKernelGGL(init_y, dim3(ceil_div(L->max_cols, 256), L->J), dim3(256), 0, st, *L, X.A->rank, y0, y);
   RFM_LAUNCH_CHECK();
 
   // r0 = h - A y0, beta_1 u_1 = r0, alpha_1 v_1 = A^T u_1, w_1 = v_1
@@ -753,16 +769,12 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   // batches of an even number of iterations, so the ping-pong buffers return to their start;
   // with timing requested the first two iterations of every batch are launched eagerly with
   // events around each stage (a sample of the kernels' durations inside the same solve)
-  const int64_t batch = 2 * ((opts->check_every + 1) / 2);
-  const bool timed = opts->times != nullptr;
-  const int64_t sampled = timed ? 2 : 0;
-  const bool graph = opts->use_graph != 0 && batch > sampled;
+  const int64_t batch = 2 * (((int64_t)check_every + 1) / 2);
+  const int64_t sampled = times ? 2 : 0;
+  const bool graph = use_graph && batch > sampled;
   EventPool pool;
   Graph G;
-  if (timed) {
-    *opts->times = rfm_kernel_times{};
-    RFM_HIP_TRY(pool.init((size_t)(kStages + 1) * sampled));
-  }
+  if (times) RFM_HIP_TRY(pool.init((size_t)(kStages + 1) * sampled));
   if (graph && !hs.done) {
     RFM_HIP_TRY(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
     RFM_HIP_TRY(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
@@ -773,7 +785,7 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
     if (ce != hipSuccess) return fail(RFM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
     RFM_HIP_TRY(hipGraphInstantiate(&G.ge, G.g, nullptr, nullptr, 0));
   }
-  while (!hs.done && i < opts->maxit) {
+  while (!hs.done && i < maxit) {
     const int64_t first = i + 1;
     for (int64_t b = 0; b < sampled; ++b) X.iteration(st, ++i, y, pool.ev.data() + (kStages + 1) * b);
     if (graph) {
@@ -791,31 +803,176 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
         float ms = 0.f;
         const size_t e0 = (size_t)(kStages + 1) * b + k;
         RFM_HIP_TRY(hipEventElapsedTime(&ms, pool.ev[e0], pool.ev[e0 + 1]));
-        opts->times->ms[k] += ms;
-        opts->times->launches[k] += 1;
+        times->ms[k] += ms;
+        times->launches[k] += 1;
       }
   }
+  *out = hs;
+  return RFM_OK;
+}
 
-  // explicit residuals: r = h - A y, A^T r
+// Explicit residuals of y with the launcher's operator and right-hand side X.h:
+// out->rnorm = ||h - A y||, out->hnorm = ||h||, out->artnorm = ||A^T r||, out->ynorm = ||y||.
+// The residual is left in X.W.res.
+rfm_status explicit_check(Launcher &X, const double *y, hipStream_t st, State *out) {
   X.fwd(st, y, X.W.st2, RESID);
   X.gather(st, nullptr, X.W.res, X.W.st2, RESID);
   X.reduce(st, X.g_rows(), X.W.st2, R_CHK_R);
   X.adj(st, X.W.res, nullptr, X.W.z, X.W.st2, RESID);
   X.reduce(st, X.n_adj_part(), X.W.st2, R_CHK_AT);
+  hipLaunchKernelGGL(sq_partials, dim3(X.g_cols()), dim3(kVecThreads), 0, st, X.L->ncols, y, X.W.part);
+  X.reduce(st, X.g_cols(), X.W.st2, R_Y_INIT);
   RFM_LAUNCH_CHECK();
-  State hc{};
-  RFM_HIP_TRY(hipMemcpyAsync(&hc, X.W.st2, sizeof(State), hipMemcpyDeviceToHost, st));
+  RFM_HIP_TRY(hipMemcpyAsync(out, X.W.st2, sizeof(State), hipMemcpyDeviceToHost, st));
   RFM_HIP_TRY(hipStreamSynchronize(st));
+  return RFM_OK;
+}
+
+}  // namespace
+}  // namespace rfm
+
+extern "C" size_t rfm_lsqr_ws_bytes(const rfm_layout *L) {
+  if (!L) return 0;
+  return rfm::carve(L, nullptr, nullptr);
+}
+
+extern "C" rfm_status rfm_pack_q(const rfm_layout *L, const int32_t *rank, const double *Q, int32_t dtype,
+                                 void *Qlow, void *stream) {
+  using namespace rfm;
+  rfm_status s0 = check_layout(L, "rfm_pack_q");
+  if (s0 != RFM_OK) return s0;
+  if (dtype != RFM_F32 && dtype != RFM_BF16) return fail(RFM_EINVAL, "rfm_pack_q: dtype must be RFM_F32 or RFM_BF16");
+  if (!rank || (L->nnz > 0 && (!Q || !Qlow))) return fail(RFM_EINVAL, "rfm_pack_q: null pointer");
+  if (L->max_rows <= 0) return RFM_OK;
+  const dim3 grid(ceil_div(L->max_rows, kRowTile), L->J);
+  if (dtype == RFM_F32)
+    hipLaunchKernelGGL(pack_q<float>, grid, dim3(kRowTile), 0, (hipStream_t)stream, *L, rank, Q, (float *)Qlow);
+  else
+    hipLaunchKernelGGL(pack_q<bf16_t>, grid, dim3(kRowTile), 0, (hipStream_t)stream, *L, rank, Q, (bf16_t *)Qlow);
+  RFM_LAUNCH_CHECK();
+  return RFM_OK;
+}
+
+extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A, const double *h,
+                                     const double *y0, const rfm_lsqr_opts *opts, double *y,
+                                     rfm_lsqr_info *info, void *ws, size_t ws_bytes, void *stream) {
+  using namespace rfm;
+  rfm_status s0 = check_layout(L, "rfm_lsqr_solve");
+  if (s0 != RFM_OK) return s0;
+  if (!A || !A->rank || !opts || !h || !y || !info) return fail(RFM_EINVAL, "rfm_lsqr_solve: null pointer");
+  if (A->form != RFM_FORM_Q && A->form != RFM_FORM_R) return fail(RFM_EINVAL, "rfm_lsqr_solve: bad form");
+  if (A->form == RFM_FORM_Q && L->nnz > 0 && !A->Q) return fail(RFM_EINVAL, "rfm_lsqr_solve: null Q");
+  if (A->form == RFM_FORM_R && ((L->nnz > 0 && !A->M) || !A->kept || (L->nrsq > 0 && !A->R)))
+    return fail(RFM_EINVAL, "rfm_lsqr_solve: R form needs M, kept and R");
+  if (opts->maxit < 1 || opts->check_every < 1 || !(opts->atol >= 0) || !(opts->btol >= 0))
+    return fail(RFM_EINVAL, "rfm_lsqr_solve: bad options");
+  const bool mixed = opts->inner_dtype != RFM_F64;
+  if (mixed) {
+    if (opts->inner_dtype != RFM_F32 && opts->inner_dtype != RFM_BF16)
+      return fail(RFM_EINVAL, "rfm_lsqr_solve: inner_dtype must be RFM_F64, RFM_F32 or RFM_BF16");
+    if (!A->Qlow || A->low_dtype != opts->inner_dtype)
+      return fail(RFM_EINVAL, "rfm_lsqr_solve: the operator needs Qlow packed in inner_dtype");
+    if (opts->max_outer < 1 || opts->max_inner < 1 || !(opts->inner_tol > 0 && opts->inner_tol < 1))
+      return fail(RFM_EINVAL, "rfm_lsqr_solve: bad refinement options");
+  }
+  if (ws_bytes < rfm_lsqr_ws_bytes(L) || !ws) return fail(RFM_EINVAL, "rfm_lsqr_solve: workspace too small");
+  if ((size_t)L->max_rows * sizeof(double) + (size_t)L->max_cols * sizeof(int) > 120 * 1024 ||
+      ((size_t)L->max_cols + kTri * kTri) * sizeof(double) > 120 * 1024)
+    return fail(RFM_EUNSUPPORTED, "rfm_lsqr_solve: block too large for LDS staging");
+  hipStream_t st = (hipStream_t)stream;
+
+  Launcher X;
+  X.L = L;
+  X.A = A;
+  X.h = h;
+  X.ct = adj_tile(L);
+  X.rform = (A->form == RFM_FORM_R);
+  carve(L, (char *)ws, &X.W);
+
+  // ||A||_F = sqrt(sum_j r_j): the Q form has unit-norm columns
+  std::vector<int32_t> hrank(L->J);
+  RFM_HIP_TRY(hipMemcpyAsync(hrank.data(), A->rank, sizeof(int32_t) * L->J, hipMemcpyDeviceToHost, st));
+  RFM_HIP_TRY(hipStreamSynchronize(st));
+  double nr = 0.0;
+  for (int32_t j = 0; j < L->J; ++j) nr += hrank[j];
+  const double anorm = std::sqrt(nr);
+  if (opts->times) *opts->times = rfm_kernel_times{};
+
+  State hs{}, hc{};
+  int64_t outer = 0;
+  info->polish = 0;
+  if (!mixed) {
+    rfm_status s = run_lsqr(X, anorm, y0, y, opts->atol, opts->btol, opts->maxit, opts->check_every,
+                            opts->use_graph != 0, opts->times, opts->history, st, &hs);
+    if (s != RFM_OK) return s;
+    s = explicit_check(X, y, st, &hc);
+    if (s != RFM_OK) return s;
+  } else {
+    // Refinement: the residual and the stopping test in binary64 with the full operator,
+    // corrections from LSQR on the narrow copy of Q_hat (products accumulated in binary32).
+    Launcher Xl = X;
+    Xl.dtype = opts->inner_dtype;
+    Xl.Qlow = A->Qlow;
+    Xl.h = X.W.res;
+    hipLaunchKernelGGL(init_y, dim3(ceil_div(L->max_cols > 0 ? L->max_cols : 1, 256), L->J), dim3(256), 0, st,
+                       *L, A->rank, y0, y);
+    RFM_LAUNCH_CHECK();
+    int64_t inner_total = 0, budget = opts->maxit;
+    double prev_at = INFINITY;
+    bool polish = false;
+    hs.stop = 3;
+    for (;; ++outer) {
+      rfm_status s = explicit_check(X, y, st, &hc);
+      if (s != RFM_OK) return s;
+      const double rn = hc.rnorm, hn = hc.hnorm;
+      if (rn == 0.0 || hc.artnorm == 0.0) { hs.stop = 4; break; }
+      if (rn <= opts->btol * hn + opts->atol * anorm * hc.ynorm) { hs.stop = 1; break; }
+      if (hc.artnorm <= opts->atol * anorm * rn) { hs.stop = 2; break; }
+      if (budget <= 0) { hs.stop = 3; break; }
+      // refinement through the narrow operator converges to A_low^T (h - A y) = 0, so once the
+      // binary64 gradient stops falling the solve is finished by binary64 LSQR from y
+      if (outer >= opts->max_outer || hc.artnorm > 0.5 * prev_at) { polish = true; break; }
+      prev_at = hc.artnorm;
+      State hi{};
+      const int64_t cap = opts->max_inner < budget ? opts->max_inner : budget;
+      s = run_lsqr(Xl, anorm, nullptr, X.W.dy, opts->inner_tol, opts->inner_tol, cap, opts->check_every,
+                   opts->use_graph != 0, opts->times, nullptr, st, &hi);
+      if (s != RFM_OK) return s;
+      inner_total += hi.iter;
+      budget -= hi.iter;
+      hipLaunchKernelGGL(axpy_inplace, dim3(ceil_div(L->ncols, 256)), dim3(256), 0, st, L->ncols, X.W.dy, y);
+      RFM_LAUNCH_CHECK();
+    }
+    int64_t polish_iters = 0;
+    if (polish) {
+      State hp{};
+      rfm_status s = run_lsqr(X, anorm, y, y, opts->atol, opts->btol, budget, opts->check_every,
+                              opts->use_graph != 0, nullptr, nullptr, st, &hp);
+      if (s != RFM_OK) return s;
+      s = explicit_check(X, y, st, &hc);
+      if (s != RFM_OK) return s;
+      polish_iters = hp.iter;
+      hs.stop = hp.stop;
+    }
+    hs.iter = inner_total + polish_iters;
+    info->polish = polish_iters;
+    hs.rnorm = hc.rnorm;
+    hs.artnorm = hc.artnorm;
+    hs.hnorm = hc.hnorm;
+    hs.ynorm = hc.ynorm;
+    hs.anorm = anorm;
+  }
 
   info->iters = hs.iter;
   info->stop = hs.stop;
+  info->outer = outer;
   info->rnorm_est = hs.rnorm;
   info->artnorm_est = hs.artnorm;
-  info->anorm = hs.anorm;
-  info->hnorm = hs.hnorm;
-  info->ynorm = hs.ynorm;
+  info->anorm = anorm;
+  info->hnorm = hc.hnorm;
+  info->ynorm = hc.ynorm;
   info->relres = hc.hnorm > 0 ? hc.rnorm / hc.hnorm : 0.0;
-  info->eta = (hc.rnorm > 0 && hs.anorm > 0) ? hc.artnorm / (hs.anorm * hc.rnorm) : 0.0;
+  info->eta = (hc.rnorm > 0 && anorm > 0) ? hc.artnorm / (anorm * hc.rnorm) : 0.0;
   return hs.stop == 3 ? RFM_ENOTCONV : RFM_OK;
 }
 

@@ -21,6 +21,7 @@ _lib = C.CDLL(_LIB_PATH)
 
 RFM_OK, RFM_EINVAL, RFM_EHIP, RFM_ENOTCONV, RFM_EUNSUPPORTED = 0, 1, 3, 4, 5
 FORM_Q, FORM_R = 0, 1
+F64, F32, BF16 = 0, 1, 2
 
 _p = C.c_void_p
 _i64p = C.POINTER(C.c_int64)
@@ -42,7 +43,8 @@ class Problem(C.Structure):
 
 
 class Operator(C.Structure):
-    _fields_ = [("form", C.c_int32), ("rank", _p), ("Q", _p), ("M", _p), ("kept", _p), ("R", _p)]
+    _fields_ = [("form", C.c_int32), ("rank", _p), ("Q", _p), ("M", _p), ("kept", _p), ("R", _p),
+                ("Qlow", _p), ("low_dtype", C.c_int32)]
 
 
 class KernelTimes(C.Structure):
@@ -56,11 +58,13 @@ class KernelTimes(C.Structure):
 class LsqrOpts(C.Structure):
     _fields_ = [("atol", C.c_double), ("btol", C.c_double), ("maxit", C.c_int64),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("times", C.POINTER(KernelTimes)), ("history", _p)]
+                ("times", C.POINTER(KernelTimes)), ("history", _p), ("inner_dtype", C.c_int32),
+                ("max_outer", C.c_int32), ("max_inner", C.c_int64), ("inner_tol", C.c_double)]
 
 
 class LsqrInfo(C.Structure):
-    _fields_ = [("iters", C.c_int64), ("stop", C.c_int32), ("rnorm_est", C.c_double),
+    _fields_ = [("iters", C.c_int64), ("outer", C.c_int64), ("polish", C.c_int64), ("stop", C.c_int32),
+                ("rnorm_est", C.c_double),
                 ("artnorm_est", C.c_double), ("anorm", C.c_double), ("hnorm", C.c_double),
                 ("ynorm", C.c_double), ("relres", C.c_double), ("eta", C.c_double)]
 
@@ -85,6 +89,8 @@ _lib.rfm_lsqr_ws_bytes.argtypes = [C.POINTER(Layout)]
 _lib.rfm_lsqr_solve.restype = C.c_int
 _lib.rfm_lsqr_solve.argtypes = [C.POINTER(Layout), C.POINTER(Operator), _p, _p, C.POINTER(LsqrOpts),
                                 _p, C.POINTER(LsqrInfo), _p, C.c_size_t, _p]
+_lib.rfm_pack_q.restype = C.c_int
+_lib.rfm_pack_q.argtypes = [C.POINTER(Layout), _p, _p, C.c_int32, _p, _p]
 _lib.rfm_coefficients.restype = C.c_int
 _lib.rfm_coefficients.argtypes = [C.POINTER(Layout), _p, _p, _p, _p, _p, _p]
 _lib.rfm_last_error.restype = C.c_char_p
@@ -92,7 +98,7 @@ _lib.rfm_last_error.argtypes = []
 
 EXPORTED = ["rfm_plan", "rfm_assemble_ws_bytes", "rfm_assemble", "rfm_rrqr_ws_bytes",
             "rfm_rrqr_filter", "rfm_lsqr_ws_bytes", "rfm_lsqr_solve", "rfm_coefficients",
-            "rfm_last_error"]
+            "rfm_pack_q", "rfm_last_error"]
 
 
 class RfmError(RuntimeError):
@@ -209,24 +215,38 @@ def rfm_rrqr_filter(plan: Plan, M, tau, with_ratios=True, out=None):
     return out
 
 
+def rfm_pack_q(plan: Plan, fact: dict, dtype, Qlow=None):
+    """Narrow copy of Q_hat (binary32 or bfloat16) in the block layout."""
+    L = plan.layout
+    tdt = {F32: torch.float32, BF16: torch.bfloat16}[dtype]
+    Qlow = torch.zeros(max(L.nnz, 1), dtype=tdt, device=fact["Q"].device) if Qlow is None else Qlow
+    _check(_lib.rfm_pack_q(C.byref(L), _ptr(fact["rank"]), _ptr(fact["Q"]), dtype, _ptr(Qlow), _stream()),
+           "rfm_pack_q")
+    return Qlow
+
+
 def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, maxit=10000,
                    check_every=16, use_graph=0, form=FORM_Q, y=None, ws=None, times=None,
-                   history=None):
+                   history=None, inner_dtype=F64, max_outer=20, max_inner=100000, inner_tol=1e-4):
     L = plan.layout
     dev = h.device
     y = torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if y is None else y
+    qlow = fact.get("Qlow")
+    low_dtype = {torch.float32: F32, torch.bfloat16: BF16}.get(qlow.dtype, F64) if qlow is not None else F64
     op = Operator(form=form, rank=fact["rank"].data_ptr(), Q=fact["Q"].data_ptr(),
                   M=fact["M"].data_ptr() if fact.get("M") is not None else 0,
-                  kept=fact["kept"].data_ptr(), R=fact["R"].data_ptr())
+                  kept=fact["kept"].data_ptr(), R=fact["R"].data_ptr(),
+                  Qlow=qlow.data_ptr() if qlow is not None else 0, low_dtype=low_dtype)
     opts = LsqrOpts(atol=atol, btol=btol, maxit=maxit, check_every=check_every, use_graph=use_graph,
-                    times=C.pointer(times) if times is not None else None, history=_ptr(history))
+                    times=C.pointer(times) if times is not None else None, history=_ptr(history),
+                    inner_dtype=inner_dtype, max_outer=max_outer, max_inner=max_inner, inner_tol=inner_tol)
     info = LsqrInfo()
     nb = _lib.rfm_lsqr_ws_bytes(C.byref(L))
     if ws is None or ws.numel() < nb:
         ws = _ws(nb, dev)
-    st = _check(_lib.rfm_lsqr_solve(C.byref(L), C.byref(op), _ptr(h), _ptr(y0), C.byref(opts), _ptr(y),
-                                    C.byref(info), _ptr(ws), nb, _stream()), "rfm_lsqr_solve",
-                allow=(RFM_ENOTCONV,))
+    _check(_lib.rfm_lsqr_solve(C.byref(L), C.byref(op), _ptr(h), _ptr(y0), C.byref(opts), _ptr(y),
+                               C.byref(info), _ptr(ws), nb, _stream()), "rfm_lsqr_solve",
+           allow=(RFM_ENOTCONV,))
     return y, info
 
 

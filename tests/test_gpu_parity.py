@@ -345,3 +345,53 @@ def test_lsqr_r_form_matches_oracle_r_form(rfm, name):
     rel = np.linalg.norm(y.cpu().numpy() - ypad) / np.linalg.norm(ypad)
     print(f"  converged: iters gpu {info.iters} oracle {info_or.iters}, rel diff {rel:.2e}", flush=True)
     assert rel <= tol
+
+
+def _shared_fact(rfm, inst, tau):
+    rows, blocks, h = assembly.assemble(inst)
+    facts = rrqr.filter_blocks(blocks, tau)
+    plan = rfm.plan_instance(inst)
+    K = np.diff(inst.feat_off)
+    fact = dict(rank=_dev(np.array([f.rank for f in facts]), torch.int32),
+                kept=_dev(H.pack_kept(plan.host, facts, K), torch.int32),
+                R=_dev(H.pack_r(plan.host, facts, K)), Q=_dev(H.pack_q(plan.host, facts, K)))
+    return rows, blocks, h, facts, plan, fact
+
+
+@pytest.mark.parametrize("name", ["poisson2d", "helmholtz2d_uneven"])
+def test_pack_q_rounding_bitwise(rfm, name):
+    from oracle import forms
+    inst = I.tiny(name)
+    rows, blocks, h, facts, plan, fact = _shared_fact(rfm, inst, 1e-10)
+    K = np.diff(inst.feat_off)
+    for dt, rnd in ((rfm.F32, forms.round_f32), (rfm.BF16, forms.round_bf16)):
+        ql = rfm.rfm_pack_q(plan, fact, dt)
+        torch.cuda.synchronize()
+        got = ql.to(torch.float32).cpu().numpy()
+        for j, f in enumerate(facts):
+            g = H.unpack_block(got, plan.host, j, K)[:, :f.rank]
+            assert np.array_equal(g.view(np.uint32), rnd(f.Q).view(np.uint32)), (dt, j)
+
+
+@pytest.mark.parametrize("dtype,name,tau", [("f32", "heat3d", 1e-10), ("f32", "poisson1d", 1e-8),
+                                            ("bf16", "poisson2d", 1e-1), ("bf16", "heat3d", 1e-10)])
+def test_precision_form_reaches_binary64_solution(rfm, dtype, name, tau):
+    """Refinement around the narrow operator plus the binary64 finish gives the binary64
+    least-squares solution (compared with the oracle's dense solve)."""
+    inst = I.tiny(name)
+    print(f"[mixed] {dtype} {name} tau={tau}", flush=True)
+    rows, blocks, h, facts, plan, fact = _shared_fact(rfm, inst, tau)
+    fact["Qlow"] = rfm.rfm_pack_q(plan, fact, rfm.F32 if dtype == "f32" else rfm.BF16)
+    A = olsqr.QForm(inst.N, rows, [f.Q for f in facts])
+    D = np.stack([A.matvec(e) for e in np.eye(A.n)], axis=1)
+    ystar = np.linalg.lstsq(D, h, rcond=None)[0]
+    kappa = np.linalg.cond(D)
+    y, info = rfm.rfm_lsqr_solve(plan, fact, _dev(h), atol=1e-12, btol=1e-12, maxit=50000,
+                                 inner_dtype=rfm.F32 if dtype == "f32" else rfm.BF16, inner_tol=1e-6)
+    torch.cuda.synchronize()
+    ypad = H.pack_y(inst.feat_off, facts, ystar)
+    rel = np.linalg.norm(y.cpu().numpy() - ypad) / np.linalg.norm(ypad)
+    print(f"  outer {info.outer} iters {info.iters} (finish {info.polish}) stop {info.stop} rel {rel:.2e} "
+          f"kappa {kappa:.1e}", flush=True)
+    assert info.stop in (1, 2, 4)
+    assert rel <= 1e-9 * kappa
