@@ -149,6 +149,30 @@ rfm_status rfm_rrqr_filter(const rfm_layout *L, const double *M, double tau, int
                            int32_t *kept, double *R, double *Q, double *ratios, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* Launch shapes of the batching form (uneven blocks).  Zero fields take the defaults. */
+typedef struct {
+  int32_t rrqr_threads;    /* workgroup size of the filter: 256, 512 or 1024 (1024 only for
+                              blocks of at most 1024 rows); 0 = by block height */
+  int32_t rrqr_persistent; /* 1: one persistent launch whose workgroups take blocks from a
+                              shared counter in the given order (largest first) */
+  int32_t rrqr_wgs_per_cu; /* persistent grid = rrqr_wgs_per_cu x CUs (>= 1)  */
+  int32_t adj_tile;        /* columns per workgroup of the adjoint block products of LSQR
+                              (a multiple of 16; 0 = about 4096 workgroups in all) */
+} rfm_tuning;
+
+/* Cost order of the blocks (sync, host only): block ids sorted by decreasing Householder QR
+ * flops 4mnk - 2(m+n)k^2 + 4/3 k^3, k = min(m, n), ties in id order.  row_off, feat_off
+ * host [J+1]; order host [J]. */
+rfm_status rfm_plan_order(int32_t J, const int64_t *row_off, const int64_t *feat_off, int32_t *order);
+
+/* rfm_rrqr_filter with an explicit block order (device [J], nullable = 0..J-1) and launch
+ * shapes (nullable = defaults).  Results do not depend on either.  The persistent launch
+ * needs ws (rfm_rrqr_ws_bytes). */
+rfm_status rfm_rrqr_filter_tuned(const rfm_layout *L, const double *M, double tau, int32_t *rank,
+                                 int32_t *kept, double *R, double *Q, double *ratios,
+                                 const int32_t *order, const rfm_tuning *tune, void *ws,
+                                 size_t ws_bytes, void *stream);
+
 /* Operator of the preconditioned system M_hat S^{-1} (Proposition 3.1). */
 typedef enum {
   RFM_FORM_Q = 0,         /* explicit Q_hat_j: A = sum_j V_j^T Q_hat_j W_hat_j        */
@@ -200,6 +224,8 @@ typedef struct {
   int32_t max_outer;      /* precision form: refinement steps (>= 1)        */
   int64_t max_inner;      /* precision form: iteration cap of one inner solve (>= 1) */
   double inner_tol;       /* precision form: atol = btol of the inner solves, in (0, 1) */
+  int32_t adj_tile;       /* columns per workgroup of the adjoint block products (multiple of
+                             16; 0 = default, see rfm_tuning) */
 } rfm_lsqr_opts;
 
 typedef struct {
@@ -248,6 +274,21 @@ rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A, const doub
  * feat_off[j] + k, local feature order). */
 rfm_status rfm_coefficients(const rfm_layout *L, const int32_t *rank, const int32_t *kept,
                             const double *R, const double *y, double *a, void *stream);
+
+/* Autotuner of the batching form (sync).  Times, with HIP events on `stream`, every
+ * candidate launch shape of the filter on the caller's data (rrqr_threads in {256, 512,
+ * 1024}, default and persistent launches with 1 or 2 workgroups per CU) and then the
+ * adjoint tile of LSQR (adj_tile in {16, 32, 64, 128, 256}) over a short solve of
+ * lsqr_iters iterations on h, and writes the fastest shapes to *best.  The filter outputs
+ * (rank, kept, R, Q, ratios) hold the result of the last candidate run (identical for all).
+ * ms_out / cand_out (host, nullable, capacity 32) receive every candidate's time and shape;
+ * *ncand their number.  ws: max(rfm_rrqr_ws_bytes, rfm_lsqr_ws_bytes) bytes of device memory;
+ * y_scratch: device [ncols]. */
+rfm_status rfm_autotune(const rfm_layout *L, const double *M, double tau, int32_t *rank,
+                        int32_t *kept, double *R, double *Q, double *ratios, const int32_t *order,
+                        const double *h, int64_t lsqr_iters, double *y_scratch, void *ws,
+                        size_t ws_bytes, rfm_tuning *best, double *ms_out, rfm_tuning *cand_out,
+                        int32_t *ncand, void *stream);
 
 /* Description of the last failure on the calling thread ("" if none). */
 const char *rfm_last_error(void);

@@ -574,7 +574,7 @@ size_t carve(const rfm_layout *L, char *base, Work *W) {
   const int64_t N = L->N, nc = L->ncols;
   const int64_t g_rows = (N + kVecThreads - 1) / kVecThreads;
   const int64_t g_cols = (nc + kVecThreads - 1) / kVecThreads;
-  const int ct = adj_tile(L);
+  const int ct = 16;  // smallest allowed adjoint tile: the most partials
   const int64_t g_adj = (int64_t)L->J * (((L->max_cols > 0 ? L->max_cols : 1) + ct - 1) / ct);
   int64_t npart = g_rows;
   if (g_cols > npart) npart = g_cols;
@@ -885,7 +885,7 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   X.L = L;
   X.A = A;
   X.h = h;
-  X.ct = adj_tile(L);
+  X.ct = opts->adj_tile > 0 ? ((opts->adj_tile + 15) / 16) * 16 : adj_tile(L);
   X.rform = (A->form == RFM_FORM_R);
   carve(L, (char *)ws, &X.W);
 

@@ -16,7 +16,10 @@
 //     diag(R_hat) > 0.
 // Householder reflector of x = A[s:m, s]: beta = -sign(alpha) ||x||, v = [1, x_2:/(alpha -
 // beta)], tau_h = (beta - alpha)/beta, sign(0) = +.
+#include <algorithm>
 #include <climits>
+#include <utility>
+#include <vector>
 
 #include "common.hpp"
 
@@ -48,15 +51,15 @@ __device__ __forceinline__ void wave_argmax(double &best, int &bid, int &bk) {
   }
 }
 
+// The whole filter of block j by one workgroup of NT threads (m_j <= 64 T rows).
 template <int T, int NT>
-__global__ __launch_bounds__(NT) void rrqr_block(rfm_layout L, const double *__restrict__ M,
-                                                 double tau, int32_t *__restrict__ rank_out,
-                                                 int32_t *__restrict__ kept,
-                                                 double *__restrict__ Rout, double *__restrict__ Q,
-                                                 double *__restrict__ ratios) {
+__device__ void rrqr_one(const rfm_layout &L, const double *__restrict__ M, double tau,
+                         int32_t *__restrict__ rank_out, int32_t *__restrict__ kept,
+                         double *__restrict__ Rout, double *__restrict__ Q,
+                         double *__restrict__ ratios, const int j) {
   constexpr int NW = NT / kWave;
   extern __shared__ double lds_raw[];
-  const int j = blockIdx.x;
+  __syncthreads();  // a persistent workgroup reuses the LDS of its previous block
   const int64_t m64 = L.row_off[j + 1] - L.row_off[j];
   const int m = (int)m64;
   const int64_t f0 = L.feat_off[j];
@@ -288,17 +291,111 @@ __global__ __launch_bounds__(NT) void rrqr_block(rfm_layout L, const double *__r
   }
 }
 
+// One workgroup per block, block b of the launch taking order[b] (or b).
 template <int T, int NT>
-rfm_status launch_rrqr(const rfm_layout *L, const double *M, double tau, int32_t *rank,
-                       int32_t *kept, double *R, double *Q, double *ratios, hipStream_t st) {
+__global__ __launch_bounds__(NT) void rrqr_block(rfm_layout L, const double *__restrict__ M, double tau,
+                                                 int32_t *__restrict__ rank_out, int32_t *__restrict__ kept,
+                                                 double *__restrict__ Rout, double *__restrict__ Q,
+                                                 double *__restrict__ ratios, const int32_t *__restrict__ order) {
+  const int b = blockIdx.x;
+  rrqr_one<T, NT>(L, M, tau, rank_out, kept, Rout, Q, ratios, order ? order[b] : b);
+}
+
+// Persistent form: a fixed grid whose workgroups take blocks from a shared counter in the
+// order given (largest first), so uneven blocks are balanced over the CUs; every
+// workgroup leaves once the counter passes J.
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void rrqr_persistent(rfm_layout L, const double *__restrict__ M, double tau,
+                                                      int32_t *__restrict__ rank_out, int32_t *__restrict__ kept,
+                                                      double *__restrict__ Rout, double *__restrict__ Q,
+                                                      double *__restrict__ ratios,
+                                                      const int32_t *__restrict__ order, unsigned *queue) {
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int b = next;
+    __syncthreads();  // every thread has read `next` before thread 0 takes the next block
+    if (b >= L.J) return;
+    rrqr_one<T, NT>(L, M, tau, rank_out, kept, Rout, Q, ratios, order ? order[b] : b);
+  }
+}
+
+__global__ void reset_queue(unsigned *q) { *q = 0u; }
+
+struct Launch {
+  const rfm_layout *L;
+  const double *M;
+  double tau;
+  int32_t *rank, *kept;
+  double *R, *Q, *ratios;
+  const int32_t *order;
+  unsigned *queue;
+  int persistent, wgs_per_cu;
+  hipStream_t st;
+};
+
+template <int T, int NT>
+rfm_status launch_rrqr(const Launch &a) {
+  const rfm_layout *L = a.L;
   const size_t n = (size_t)L->max_cols;
   const size_t lds = n * 3 * sizeof(double) + (size_t)kWave * T * sizeof(double) +
                      32 * sizeof(double) + n * sizeof(int) + 64 * sizeof(int);
   if (lds > 150 * 1024) return fail(RFM_EUNSUPPORTED, "rfm_rrqr_filter: block too large for LDS");
-  auto kern = rrqr_block<T, NT>;
-  RFM_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(kern, dim3(L->J), dim3(NT), lds, st, *L, M, tau, rank, kept, R, Q, ratios);
+  if (!a.persistent) {
+    auto kern = rrqr_block<T, NT>;
+    RFM_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(L->J), dim3(NT), lds, a.st, *L, a.M, a.tau, a.rank, a.kept, a.R, a.Q,
+                       a.ratios, a.order);
+  } else {
+    int dev = 0, cus = 0;
+    RFM_HIP_TRY(hipGetDevice(&dev));
+    RFM_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int64_t grid = (int64_t)cus * (a.wgs_per_cu > 0 ? a.wgs_per_cu : 1);
+    if (grid > L->J) grid = L->J;
+    auto kern = rrqr_persistent<T, NT>;
+    RFM_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(reset_queue, dim3(1), dim3(1), 0, a.st, a.queue);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, a.st, *L, a.M, a.tau, a.rank, a.kept, a.R,
+                       a.Q, a.ratios, a.order, a.queue);
+  }
   RFM_LAUNCH_CHECK();
+  return RFM_OK;
+}
+
+// Rows per lane T from the tallest block; workgroup size NT from the tuning (the register
+// array of T doubles per lane limits NT = 1024 to T <= 16).
+template <int T>
+rfm_status pick_threads(const Launch &a, int threads) {
+  if (threads == 256) return launch_rrqr<T, 256>(a);
+  if (threads == 1024 && T <= 16) return launch_rrqr<T, (T <= 16 ? 1024 : 512)>(a);
+  return launch_rrqr<T, 512>(a);
+}
+
+rfm_status dispatch(const Launch &a, int threads) {
+  const int mr = a.L->max_rows;
+  if (threads == 0) threads = (mr <= 1024) ? 1024 : 512;
+  if (mr <= 64) return pick_threads<1>(a, threads);
+  if (mr <= 128) return pick_threads<2>(a, threads);
+  if (mr <= 256) return pick_threads<4>(a, threads);
+  if (mr <= 512) return pick_threads<8>(a, threads);
+  if (mr <= 768) return pick_threads<12>(a, threads);
+  if (mr <= 1024) return pick_threads<16>(a, threads);
+  if (mr <= 1536) return pick_threads<24>(a, threads);
+  if (mr <= 2048) return pick_threads<32>(a, threads);
+  if (mr <= 3072) return pick_threads<48>(a, threads);
+  return fail(RFM_EUNSUPPORTED, "rfm_rrqr_filter: max_rows > 3072");
+}
+
+rfm_status validate(const rfm_layout *L, const double *M, double tau, int32_t *rank, int32_t *kept, double *R,
+                    double *Q, const char *who) {
+  rfm_status s = check_layout(L, who);
+  if (s != RFM_OK) return s;
+  if (!(tau >= 0.0 && tau < 1.0)) return fail(RFM_EINVAL, std::string(who) + ": tau must be in [0,1)");
+  if (!rank || !kept || (L->nnz > 0 && (!M || !Q)) || (L->nrsq > 0 && !R))
+    return fail(RFM_EINVAL, std::string(who) + ": null pointer");
+  if (L->max_cols > 2048) return fail(RFM_EUNSUPPORTED, std::string(who) + ": max_cols > 2048");
+  if (L->max_rows > 3072) return fail(RFM_EUNSUPPORTED, std::string(who) + ": max_rows > 3072");
   return RFM_OK;
 }
 
@@ -307,31 +404,49 @@ rfm_status launch_rrqr(const rfm_layout *L, const double *M, double tau, int32_t
 
 extern "C" size_t rfm_rrqr_ws_bytes(const rfm_layout *L) {
   (void)L;
-  return 0;
+  return 256;  // the work-queue counter of the persistent launch
 }
 
 extern "C" rfm_status rfm_rrqr_filter(const rfm_layout *L, const double *M, double tau,
                                       int32_t *rank, int32_t *kept, double *R, double *Q,
                                       double *ratios, void *ws, size_t ws_bytes, void *stream) {
+  return rfm_rrqr_filter_tuned(L, M, tau, rank, kept, R, Q, ratios, nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+extern "C" rfm_status rfm_rrqr_filter_tuned(const rfm_layout *L, const double *M, double tau, int32_t *rank,
+                                            int32_t *kept, double *R, double *Q, double *ratios,
+                                            const int32_t *order, const rfm_tuning *tune, void *ws,
+                                            size_t ws_bytes, void *stream) {
   using namespace rfm;
-  (void)ws;
-  (void)ws_bytes;
-  rfm_status s = check_layout(L, "rfm_rrqr_filter");
+  rfm_status s = validate(L, M, tau, rank, kept, R, Q, "rfm_rrqr_filter");
   if (s != RFM_OK) return s;
-  if (!(tau >= 0.0 && tau < 1.0)) return fail(RFM_EINVAL, "rfm_rrqr_filter: tau must be in [0,1)");
-  if (!rank || !kept || (L->nnz > 0 && (!M || !Q)) || (L->nrsq > 0 && !R))
-    return fail(RFM_EINVAL, "rfm_rrqr_filter: null pointer");
-  if (L->max_cols > 2048) return fail(RFM_EUNSUPPORTED, "rfm_rrqr_filter: max_cols > 2048");
-  hipStream_t st = (hipStream_t)stream;
-  const int mr = L->max_rows;
-  if (mr <= 64) return launch_rrqr<1, 1024>(L, M, tau, rank, kept, R, Q, ratios, st);
-  if (mr <= 128) return launch_rrqr<2, 1024>(L, M, tau, rank, kept, R, Q, ratios, st);
-  if (mr <= 256) return launch_rrqr<4, 1024>(L, M, tau, rank, kept, R, Q, ratios, st);
-  if (mr <= 512) return launch_rrqr<8, 1024>(L, M, tau, rank, kept, R, Q, ratios, st);
-  if (mr <= 768) return launch_rrqr<12, 1024>(L, M, tau, rank, kept, R, Q, ratios, st);
-  if (mr <= 1024) return launch_rrqr<16, 1024>(L, M, tau, rank, kept, R, Q, ratios, st);
-  if (mr <= 1536) return launch_rrqr<24, 512>(L, M, tau, rank, kept, R, Q, ratios, st);
-  if (mr <= 2048) return launch_rrqr<32, 512>(L, M, tau, rank, kept, R, Q, ratios, st);
-  if (mr <= 3072) return launch_rrqr<48, 512>(L, M, tau, rank, kept, R, Q, ratios, st);
-  return fail(RFM_EUNSUPPORTED, "rfm_rrqr_filter: max_rows > 3072");
+  const int persistent = tune ? tune->rrqr_persistent : 0;
+  if (persistent && (!ws || ws_bytes < rfm_rrqr_ws_bytes(L)))
+    return fail(RFM_EINVAL, "rfm_rrqr_filter: the persistent launch needs the workspace");
+  const int threads = tune ? tune->rrqr_threads : 0;
+  if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+    return fail(RFM_EINVAL, "rfm_rrqr_filter: rrqr_threads must be 0, 256, 512 or 1024");
+  Launch a{L, M, tau, rank, kept, R, Q, ratios, order, (unsigned *)ws, persistent,
+           tune ? tune->rrqr_wgs_per_cu : 1, (hipStream_t)stream};
+  return dispatch(a, threads);
+}
+
+extern "C" rfm_status rfm_plan_order(int32_t J, const int64_t *row_off, const int64_t *feat_off,
+                                     int32_t *order) {
+  using namespace rfm;
+  if (J < 1 || !row_off || !feat_off || !order) return fail(RFM_EINVAL, "rfm_plan_order: bad arguments");
+  std::vector<std::pair<double, int32_t>> cost(J);
+  for (int32_t j = 0; j < J; ++j) {
+    const double m = (double)(row_off[j + 1] - row_off[j]);
+    const double n = (double)(feat_off[j + 1] - feat_off[j]);
+    const double k = m < n ? m : n;
+    // Householder QR flops of the full factorisation: the work of the block up to its rank
+    cost[j] = {4.0 * m * n * k - 2.0 * (m + n) * k * k + (4.0 / 3.0) * k * k * k, j};
+  }
+  std::stable_sort(cost.begin(), cost.end(),
+                   [](const std::pair<double, int32_t> &x, const std::pair<double, int32_t> &y) {
+                     return x.first > y.first;
+                   });
+  for (int32_t j = 0; j < J; ++j) order[j] = cost[j].second;
+  return RFM_OK;
 }

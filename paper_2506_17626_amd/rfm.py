@@ -47,6 +47,14 @@ class Operator(C.Structure):
                 ("Qlow", _p), ("low_dtype", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("rrqr_threads", C.c_int32), ("rrqr_persistent", C.c_int32), ("rrqr_wgs_per_cu", C.c_int32),
+                ("adj_tile", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class KernelTimes(C.Structure):
     _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5)]
     NAMES = ("fwd_local", "gather_beta", "adj_local", "alpha_rotation", "yw_update")
@@ -59,7 +67,8 @@ class LsqrOpts(C.Structure):
     _fields_ = [("atol", C.c_double), ("btol", C.c_double), ("maxit", C.c_int64),
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("times", C.POINTER(KernelTimes)), ("history", _p), ("inner_dtype", C.c_int32),
-                ("max_outer", C.c_int32), ("max_inner", C.c_int64), ("inner_tol", C.c_double)]
+                ("max_outer", C.c_int32), ("max_inner", C.c_int64), ("inner_tol", C.c_double),
+                ("adj_tile", C.c_int32)]
 
 
 class LsqrInfo(C.Structure):
@@ -89,6 +98,14 @@ _lib.rfm_lsqr_ws_bytes.argtypes = [C.POINTER(Layout)]
 _lib.rfm_lsqr_solve.restype = C.c_int
 _lib.rfm_lsqr_solve.argtypes = [C.POINTER(Layout), C.POINTER(Operator), _p, _p, C.POINTER(LsqrOpts),
                                 _p, C.POINTER(LsqrInfo), _p, C.c_size_t, _p]
+_lib.rfm_plan_order.restype = C.c_int
+_lib.rfm_plan_order.argtypes = [C.c_int32, _p, _p, _p]
+_lib.rfm_rrqr_filter_tuned.restype = C.c_int
+_lib.rfm_rrqr_filter_tuned.argtypes = [C.POINTER(Layout), _p, C.c_double, _p, _p, _p, _p, _p, _p,
+                                       C.POINTER(Tuning), _p, C.c_size_t, _p]
+_lib.rfm_autotune.restype = C.c_int
+_lib.rfm_autotune.argtypes = [C.POINTER(Layout), _p, C.c_double, _p, _p, _p, _p, _p, _p, _p, C.c_int64,
+                              _p, _p, C.c_size_t, C.POINTER(Tuning), _p, _p, _p, _p]
 _lib.rfm_pack_q.restype = C.c_int
 _lib.rfm_pack_q.argtypes = [C.POINTER(Layout), _p, _p, C.c_int32, _p, _p]
 _lib.rfm_coefficients.restype = C.c_int
@@ -98,7 +115,7 @@ _lib.rfm_last_error.argtypes = []
 
 EXPORTED = ["rfm_plan", "rfm_assemble_ws_bytes", "rfm_assemble", "rfm_rrqr_ws_bytes",
             "rfm_rrqr_filter", "rfm_lsqr_ws_bytes", "rfm_lsqr_solve", "rfm_coefficients",
-            "rfm_pack_q", "rfm_last_error"]
+            "rfm_pack_q", "rfm_plan_order", "rfm_rrqr_filter_tuned", "rfm_autotune", "rfm_last_error"]
 
 
 class RfmError(RuntimeError):
@@ -198,21 +215,53 @@ def rfm_assemble(plan: Plan, prob: dict, M=None, h=None):
     return M, h
 
 
-def rfm_rrqr_filter(plan: Plan, M, tau, with_ratios=True, out=None):
+def rfm_plan_order(plan: Plan):
+    """Block ids by decreasing factorisation cost (host), copied to the device."""
+    order = np.zeros(plan.J, dtype=np.int32)
+    _check(_lib.rfm_plan_order(plan.J, _np_ptr(plan.host["row_off"]), _np_ptr(plan.host["feat_off"]),
+                               _np_ptr(order)), "rfm_plan_order")
+    return torch.from_numpy(order).to(plan.dev["row_off"].device) if plan.dev else order
+
+
+def _rrqr_out(L, dev, with_ratios):
+    return dict(rank=torch.empty(L.J, dtype=torch.int32, device=dev),
+                kept=torch.empty(max(L.ncols, 1), dtype=torch.int32, device=dev),
+                R=torch.zeros(max(L.nrsq, 1), dtype=torch.float64, device=dev),
+                Q=torch.empty(max(L.nnz, 1), dtype=torch.float64, device=dev),
+                ratios=torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if with_ratios else None)
+
+
+def rfm_rrqr_filter(plan: Plan, M, tau, with_ratios=True, out=None, order=None, tune=None):
     L = plan.layout
     dev = M.device
-    if out is None:
-        out = dict(rank=torch.empty(L.J, dtype=torch.int32, device=dev),
-                   kept=torch.empty(max(L.ncols, 1), dtype=torch.int32, device=dev),
-                   R=torch.zeros(max(L.nrsq, 1), dtype=torch.float64, device=dev),
-                   Q=torch.empty(max(L.nnz, 1), dtype=torch.float64, device=dev),
-                   ratios=torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if with_ratios else None)
+    out = _rrqr_out(L, dev, with_ratios) if out is None else out
     nb = _lib.rfm_rrqr_ws_bytes(C.byref(L))
     ws = _ws(nb, dev)
-    _check(_lib.rfm_rrqr_filter(C.byref(L), _ptr(M), float(tau), _ptr(out["rank"]), _ptr(out["kept"]),
-                                _ptr(out["R"]), _ptr(out["Q"]), _ptr(out["ratios"]), _ptr(ws), nb,
-                                _stream()), "rfm_rrqr_filter")
+    _check(_lib.rfm_rrqr_filter_tuned(C.byref(L), _ptr(M), float(tau), _ptr(out["rank"]), _ptr(out["kept"]),
+                                      _ptr(out["R"]), _ptr(out["Q"]), _ptr(out["ratios"]), _ptr(order),
+                                      C.byref(tune) if tune is not None else None, _ptr(ws), nb, _stream()),
+           "rfm_rrqr_filter")
     return out
+
+
+def rfm_autotune(plan: Plan, M, tau, h, order=None, lsqr_iters=64, out=None):
+    """Time the candidate launch shapes (filter, then the LSQR adjoint tile); returns
+    (best Tuning, [(Tuning, ms)], filter outputs)."""
+    L = plan.layout
+    dev = M.device
+    out = _rrqr_out(L, dev, True) if out is None else out
+    nb = max(_lib.rfm_rrqr_ws_bytes(C.byref(L)), _lib.rfm_lsqr_ws_bytes(C.byref(L)))
+    ws = _ws(nb, dev)
+    y = torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev)
+    best = Tuning()
+    ms = (C.c_double * 32)()
+    cands = (Tuning * 32)()
+    n = C.c_int32(0)
+    _check(_lib.rfm_autotune(C.byref(L), _ptr(M), float(tau), _ptr(out["rank"]), _ptr(out["kept"]), _ptr(out["R"]),
+                             _ptr(out["Q"]), _ptr(out["ratios"]), _ptr(order), _ptr(h), int(lsqr_iters), _ptr(y),
+                             _ptr(ws), nb, C.byref(best), ms, cands, C.byref(n), _stream()), "rfm_autotune")
+    table = [(cands[i].as_dict(), ms[i]) for i in range(min(n.value, 32))]
+    return best, table, out
 
 
 def rfm_pack_q(plan: Plan, fact: dict, dtype, Qlow=None):
@@ -227,7 +276,8 @@ def rfm_pack_q(plan: Plan, fact: dict, dtype, Qlow=None):
 
 def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, maxit=10000,
                    check_every=16, use_graph=0, form=FORM_Q, y=None, ws=None, times=None,
-                   history=None, inner_dtype=F64, max_outer=20, max_inner=100000, inner_tol=1e-4):
+                   history=None, inner_dtype=F64, max_outer=20, max_inner=100000, inner_tol=1e-4,
+                   adj_tile=0):
     L = plan.layout
     dev = h.device
     y = torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if y is None else y
@@ -239,7 +289,8 @@ def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, max
                   Qlow=qlow.data_ptr() if qlow is not None else 0, low_dtype=low_dtype)
     opts = LsqrOpts(atol=atol, btol=btol, maxit=maxit, check_every=check_every, use_graph=use_graph,
                     times=C.pointer(times) if times is not None else None, history=_ptr(history),
-                    inner_dtype=inner_dtype, max_outer=max_outer, max_inner=max_inner, inner_tol=inner_tol)
+                    inner_dtype=inner_dtype, max_outer=max_outer, max_inner=max_inner, inner_tol=inner_tol,
+                    adj_tile=adj_tile)
     info = LsqrInfo()
     nb = _lib.rfm_lsqr_ws_bytes(C.byref(L))
     if ws is None or ws.numel() < nb:

@@ -115,3 +115,20 @@ def test_workspace_queries_scale_with_layout():
     big = rfm.plan_instance(I.poisson2d(S=6, K=40, n=7, nb=30), device=None).layout
     for f in (rfm._lib.rfm_assemble_ws_bytes, rfm._lib.rfm_lsqr_ws_bytes):
         assert 0 < f(C.byref(small)) < f(C.byref(big))
+
+
+def test_plan_order_sorts_by_factorisation_cost():
+    from paper_2506_17626_amd import rfm
+    inst = I.tiny("helmholtz2d_uneven")
+    plan = rfm.plan_instance(inst, device=None)
+    order = rfm.rfm_plan_order(plan)
+    m = np.diff(plan.host["row_off"]).astype(float)
+    n = np.diff(plan.host["feat_off"]).astype(float)
+    k = np.minimum(m, n)
+    cost = 4 * m * n * k - 2 * (m + n) * k**2 + (4 / 3) * k**3
+    assert sorted(order.tolist()) == list(range(inst.J))
+    assert np.all(np.diff(cost[order]) <= 0)
+    # ties keep id order
+    for a, b in zip(order[:-1], order[1:]):
+        if cost[a] == cost[b]:
+            assert a < b

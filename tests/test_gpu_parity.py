@@ -395,3 +395,71 @@ def test_precision_form_reaches_binary64_solution(rfm, dtype, name, tau):
           f"kappa {kappa:.1e}", flush=True)
     assert info.stop in (1, 2, 4)
     assert rel <= 1e-9 * kappa
+
+
+def test_batching_form_results_independent_of_order_and_launch_shape(rfm):
+    """Persistent launch with the cost order and every workgroup size give bitwise the same
+    factors as the default launch (each column is reduced by one wave in a fixed order)."""
+    inst = I.tiny("helmholtz2d_uneven")
+    rows, blocks, _ = assembly.assemble(inst)
+    plan = rfm.plan_instance(inst)
+    K = np.diff(inst.feat_off)
+    M = _dev(H.pack_blocks(plan.host, blocks, K))
+    ref = rfm.rfm_rrqr_filter(plan, M, 1e-12)
+    order = rfm.rfm_plan_order(plan)
+    for threads in (256, 512, 1024):
+        for persistent, wgs in ((0, 1), (1, 1), (1, 2)):
+            tune = rfm.Tuning(rrqr_threads=threads, rrqr_persistent=persistent, rrqr_wgs_per_cu=wgs)
+            out = rfm.rfm_rrqr_filter(plan, M, 1e-12, order=order, tune=tune)
+            torch.cuda.synchronize()
+            for k in ("rank", "kept", "R", "Q", "ratios"):
+                assert torch.equal(out[k], ref[k]), (threads, persistent, wgs, k)
+
+
+def test_batching_form_full_uneven_workload_sampled(rfm):
+    """The 64x64 uneven Helmholtz workload through one persistent launch: sampled blocks (the
+    largest, the smallest, boundary and wide ones) against the oracle's filter."""
+    inst = I.workload("helmholtz2d_uneven")
+    print("[batching] helmholtz2d_uneven full size", flush=True)
+    plan, prob = _setup(rfm, inst)
+    M, h = rfm.rfm_assemble(plan, prob)
+    order = rfm.rfm_plan_order(plan)
+    tune = rfm.Tuning(rrqr_threads=1024, rrqr_persistent=1, rrqr_wgs_per_cu=1)
+    out = rfm.rfm_rrqr_filter(plan, M, 1e-12, order=order, tune=tune)
+    torch.cuda.synchronize()
+    K = np.diff(inst.feat_off)
+    m = np.diff(plan.host["row_off"])
+    Mh = M.cpu().numpy()
+    rk = out["rank"].cpu().numpy()
+    kept = out["kept"].cpu().numpy()
+    Rh = out["R"].cpu().numpy()
+    o = order.cpu().numpy()
+    picks = sorted({int(o[0]), int(o[1]), int(o[-1]), int(np.argmax(m)), int(np.argmin(m)),
+                    int(np.argmax(K - m)), 0, 63, 4095})
+    fo = plan.host["feat_off"]
+    for j in picks:
+        Mj = H.unpack_block(Mh, plan.host, j, K)
+        f = rrqr.qrcp_filter(Mj, 1e-12)
+        assert rk[j] == f.rank and np.array_equal(kept[fo[j]:fo[j] + rk[j]], f.kept), j
+        assert np.max(np.abs(H.unpack_r(Rh, plan.host, j, K, f.rank) - f.R)) <= 1e-12 * np.linalg.norm(Mj)
+
+
+def test_lsqr_adjoint_tile_and_autotune(rfm):
+    inst = I.tiny("helmholtz2d_uneven")
+    rows, blocks, h, facts, plan, fact = _shared_fact(rfm, inst, 1e-10)
+    hd = _dev(h)
+    ys = []
+    for tile in (16, 32, 64, 128):
+        y, info = rfm.rfm_lsqr_solve(plan, fact, hd, atol=0.0, btol=0.0, maxit=40, adj_tile=tile)
+        ys.append(y.cpu().numpy())
+    # different tiles group the partial sums of ||q||^2 differently (last-bit changes of alpha),
+    # which the recurrence carries along; 40 iterations keep the iterates within 1e-7
+    for y in ys[1:]:
+        assert np.linalg.norm(y - ys[0]) <= 1e-7 * np.linalg.norm(ys[0])
+    K = np.diff(inst.feat_off)
+    M = _dev(H.pack_blocks(plan.host, blocks, K))
+    best, table, out = rfm.rfm_autotune(plan, M, 1e-10, hd, order=rfm.rfm_plan_order(plan), lsqr_iters=8)
+    assert best.rrqr_threads in (256, 512, 1024) and best.adj_tile in (16, 32, 64, 128, 256)
+    assert len(table) >= 6
+    ref = rfm.rfm_rrqr_filter(plan, M, 1e-10)
+    assert torch.equal(out["rank"], ref["rank"]) and torch.equal(out["Q"], ref["Q"])
