@@ -268,12 +268,61 @@ rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A, const doub
                           const double *y0, const rfm_lsqr_opts *opts, double *y,
                           rfm_lsqr_info *info, void *ws, size_t ws_bytes, void *stream);
 
+/* Bytes of device workspace rfm_lsqr_multi needs for nrhs right-hand sides. */
+size_t rfm_lsqr_multi_ws_bytes(const rfm_layout *L, int32_t nrhs);
+
+/* LSQR for nrhs (1..64) right-hand sides on the same Q-form operator (sync): one Paige-Saunders
+ * recurrence and stopping test (the rule of rfm_lsqr_solve, with opts->atol, btol, maxit;
+ * the other options are ignored) per right-hand side, sharing every pass over Q_hat, so the
+ * block products are dense matrix-matrix products.  Right-hand-side-minor layout: H device
+ * [N x nrhs], Y0 (nullable) and Y device [ncols x nrhs] (entry (j,k) of right-hand side b at
+ * (feat_off[j] + k) * nrhs + b).  A finished right-hand side is frozen while the others go on.
+ * iters, stops: host [nrhs], nullable.  RFM_ENOTCONV if any right-hand side reached maxit. */
+rfm_status rfm_lsqr_multi(const rfm_layout *L, const rfm_operator *A, const double *H, int32_t nrhs,
+                          const double *Y0, const rfm_lsqr_opts *opts, double *Y, int64_t *iters,
+                          int32_t *stops, void *ws, size_t ws_bytes, void *stream);
+
 /* Back-substitution a_hat_j = R_hat_j^{-1} y_j and scatter to the global coefficient
  * vector with zeros at dropped columns (Algorithm 2, output step).
  * y device [ncols] (layout of rfm_lsqr_solve), a device [ncols] (entry (j,k) at
  * feat_off[j] + k, local feature order). */
 rfm_status rfm_coefficients(const rfm_layout *L, const int32_t *rank, const int32_t *kept,
                             const double *R, const double *y, double *a, void *stream);
+
+/* Learned warm start (the form that maps the parameters of a PDE family to LSQR starting
+ * coordinates): a 3-layer perceptron n_in -> n_hidden -> n_hidden -> n_out with tanh hidden
+ * layers and a linear output, binary32.  Row-major parameters on the device: W1 [n_in x H],
+ * W2 [H x H], W3 [H x n_out], b1, b2 [H], b3 [n_out]; a batch of inputs X is [batch x n_in].
+ * Forward: H1 = tanh(X W1 + b1), H2 = tanh(H1 W2 + b2), Y = H2 W3 + b3. */
+typedef struct {
+  int32_t n_in, n_hidden, n_out;
+  float *W1, *b1, *W2, *b2, *W3, *b3;
+} rfm_mlp;
+
+/* Device workspace of rfm_mlp_backward for this network and batch size. */
+size_t rfm_mlp_ws_bytes(const rfm_mlp *P, int32_t batch);
+
+/* Forward pass; H1, H2 [batch x H] and Y [batch x n_out] device outputs. */
+rfm_status rfm_mlp_forward(const rfm_mlp *P, const float *X, int32_t batch, float *H1, float *H2,
+                           float *Y, void *stream);
+
+/* Backward pass of the mean squared error L = sum (Y - T)^2 / (batch n_out) given the forward
+ * activations: writes the parameter gradients into the buffers of G (same sizes as P), the
+ * loss into *loss (device float), and uses dY [batch x n_out], dH1, dH2 [batch x H] as
+ * device scratch.  Sums over the batch are taken in a fixed order. */
+rfm_status rfm_mlp_backward(const rfm_mlp *P, const rfm_mlp *G, const float *X, const float *H1,
+                            const float *H2, const float *Y, const float *T, int32_t batch,
+                            float *dY, float *dH1, float *dH2, float *loss, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* Adam (Kingma and Ba) on n parameters: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps); step >= 1. */
+rfm_status rfm_adam_step(int64_t n, float *p, const float *g, float *m, float *v, float lr,
+                         float beta1, float beta2, float eps, int32_t step, void *stream);
+
+/* out[i, :] = in[idx[i], :] for row-major [* x cols] binary32 matrices (mini-batch gather). */
+rfm_status rfm_gather_rows(int32_t rows, int32_t cols, const int32_t *idx, const float *in,
+                           float *out, void *stream);
 
 /* Autotuner of the batching form (sync).  Times, with HIP events on `stream`, every
  * candidate launch shape of the filter on the caller's data (rrqr_threads in {256, 512,

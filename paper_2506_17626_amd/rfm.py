@@ -307,3 +307,97 @@ def rfm_coefficients(plan: Plan, fact: dict, y, a=None):
     _check(_lib.rfm_coefficients(C.byref(L), _ptr(fact["rank"]), _ptr(fact["kept"]), _ptr(fact["R"]),
                                  _ptr(y), _ptr(a), _stream()), "rfm_coefficients")
     return a
+
+
+# ---------------------------------------------------------------- learned warm start (MLP)
+class Mlp(C.Structure):
+    _fields_ = [("n_in", C.c_int32), ("n_hidden", C.c_int32), ("n_out", C.c_int32), ("W1", _p), ("b1", _p),
+                ("W2", _p), ("b2", _p), ("W3", _p), ("b3", _p)]
+
+
+MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+_lib.rfm_mlp_ws_bytes.restype = C.c_size_t
+_lib.rfm_mlp_ws_bytes.argtypes = [C.POINTER(Mlp), C.c_int32]
+_lib.rfm_mlp_forward.restype = C.c_int
+_lib.rfm_mlp_forward.argtypes = [C.POINTER(Mlp), _p, C.c_int32, _p, _p, _p, _p]
+_lib.rfm_mlp_backward.restype = C.c_int
+_lib.rfm_mlp_backward.argtypes = [C.POINTER(Mlp), C.POINTER(Mlp), _p, _p, _p, _p, _p, C.c_int32, _p, _p, _p, _p,
+                                  _p, C.c_size_t, _p]
+_lib.rfm_adam_step.restype = C.c_int
+_lib.rfm_adam_step.argtypes = [C.c_int64, _p, _p, _p, _p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, _p]
+_lib.rfm_gather_rows.restype = C.c_int
+_lib.rfm_gather_rows.argtypes = [C.c_int32, C.c_int32, _p, _p, _p, _p]
+EXPORTED += ["rfm_mlp_ws_bytes", "rfm_mlp_forward", "rfm_mlp_backward", "rfm_adam_step", "rfm_gather_rows"]
+
+
+def mlp_struct(P: dict) -> Mlp:
+    n_in, n_hidden = P["W1"].shape
+    n_out = P["W3"].shape[1]
+    return Mlp(n_in=n_in, n_hidden=n_hidden, n_out=n_out, **{k: P[k].data_ptr() for k in MLP_KEYS})
+
+
+def rfm_mlp_forward(P: dict, X, H1=None, H2=None, Y=None):
+    S = mlp_struct(P)
+    B = X.shape[0]
+    H1 = torch.empty(B, S.n_hidden, dtype=torch.float32, device=X.device) if H1 is None else H1
+    H2 = torch.empty(B, S.n_hidden, dtype=torch.float32, device=X.device) if H2 is None else H2
+    Y = torch.empty(B, S.n_out, dtype=torch.float32, device=X.device) if Y is None else Y
+    _check(_lib.rfm_mlp_forward(C.byref(S), _ptr(X), B, _ptr(H1), _ptr(H2), _ptr(Y), _stream()), "rfm_mlp_forward")
+    return H1, H2, Y
+
+
+def rfm_mlp_backward(P: dict, G: dict, X, H1, H2, Y, T, scratch=None):
+    S, SG = mlp_struct(P), mlp_struct(G)
+    B = X.shape[0]
+    dev = X.device
+    if scratch is None:
+        nb = _lib.rfm_mlp_ws_bytes(C.byref(S), B)
+        scratch = dict(dY=torch.empty_like(Y), dH1=torch.empty_like(H1), dH2=torch.empty_like(H2),
+                       loss=torch.empty(1, dtype=torch.float32, device=dev), ws=_ws(nb, dev))
+    ws = scratch["ws"]
+    _check(_lib.rfm_mlp_backward(C.byref(S), C.byref(SG), _ptr(X), _ptr(H1), _ptr(H2), _ptr(Y), _ptr(T), B,
+                                 _ptr(scratch["dY"]), _ptr(scratch["dH1"]), _ptr(scratch["dH2"]),
+                                 _ptr(scratch["loss"]), _ptr(ws), ws.numel(), _stream()), "rfm_mlp_backward")
+    return scratch["loss"]
+
+
+def rfm_adam_step(p, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(_lib.rfm_adam_step(p.numel(), _ptr(p), _ptr(g), _ptr(m), _ptr(v), lr, beta1, beta2, eps, step,
+                              _stream()), "rfm_adam_step")
+
+
+def rfm_gather_rows(idx, src, out):
+    _check(_lib.rfm_gather_rows(idx.numel(), src.shape[1], _ptr(idx), _ptr(src), _ptr(out), _stream()),
+           "rfm_gather_rows")
+    return out
+
+
+# ---------------------------------------------------------------- multiple right-hand sides
+_lib.rfm_lsqr_multi_ws_bytes.restype = C.c_size_t
+_lib.rfm_lsqr_multi_ws_bytes.argtypes = [C.POINTER(Layout), C.c_int32]
+_lib.rfm_lsqr_multi.restype = C.c_int
+_lib.rfm_lsqr_multi.argtypes = [C.POINTER(Layout), C.POINTER(Operator), _p, C.c_int32, _p, C.POINTER(LsqrOpts), _p,
+                                _p, _p, _p, C.c_size_t, _p]
+EXPORTED += ["rfm_lsqr_multi_ws_bytes", "rfm_lsqr_multi"]
+
+
+def rfm_lsqr_multi(plan: Plan, fact: dict, H, Y0=None, atol=1e-8, btol=1e-8, maxit=10000, check_every=64,
+                   Y=None, ws=None):
+    """H: [N, nrhs] binary64 (right-hand-side-minor); returns Y [ncols, nrhs], iters, stops."""
+    L = plan.layout
+    B = H.shape[1]
+    dev = H.device
+    Y = torch.empty(max(L.ncols, 1), B, dtype=torch.float64, device=dev) if Y is None else Y
+    op = Operator(form=FORM_Q, rank=fact["rank"].data_ptr(), Q=fact["Q"].data_ptr(), kept=fact["kept"].data_ptr(),
+                  R=fact["R"].data_ptr())
+    opts = LsqrOpts(atol=atol, btol=btol, maxit=maxit, check_every=check_every)
+    nb = _lib.rfm_lsqr_multi_ws_bytes(C.byref(L), B)
+    if ws is None or ws.numel() < nb:
+        ws = _ws(nb, dev)
+    iters = np.zeros(B, dtype=np.int64)
+    stops = np.zeros(B, dtype=np.int32)
+    _check(_lib.rfm_lsqr_multi(C.byref(L), C.byref(op), _ptr(H), B, _ptr(Y0), C.byref(opts), _ptr(Y),
+                               _np_ptr(iters), _np_ptr(stops), _ptr(ws), nb, _stream()), "rfm_lsqr_multi",
+           allow=(RFM_ENOTCONV,))
+    return Y, iters, stops

@@ -463,3 +463,32 @@ def test_lsqr_adjoint_tile_and_autotune(rfm):
     assert len(table) >= 6
     ref = rfm.rfm_rrqr_filter(plan, M, 1e-10)
     assert torch.equal(out["rank"], ref["rank"]) and torch.equal(out["Q"], ref["Q"])
+
+
+def test_lsqr_multi_rhs_matches_oracle_per_rhs(rfm):
+    """Several right-hand sides at once: each column follows the oracle's single-RHS recurrence
+    (fixed iteration count) and converges to its own least-squares solution."""
+    inst = I.tiny("poisson2d")
+    rows, blocks, h, facts, plan, fact = _shared_fact(rfm, inst, 1e-8)
+    A = olsqr.QForm(inst.N, rows, [f.Q for f in facts])
+    rng = np.random.default_rng(5)
+    B = 5
+    Hm = np.stack([h * rng.uniform(0.5, 2.0) + 0.1 * rng.standard_normal(inst.N) for _ in range(B)], axis=1)
+    Y, iters, stops = rfm.rfm_lsqr_multi(plan, fact, _dev(Hm), atol=0.0, btol=0.0, maxit=25)
+    torch.cuda.synchronize()
+    Yg = Y.cpu().numpy()
+    assert np.all(iters == 25) and np.all(stops == 3)
+    for b in range(B):
+        yo, io = olsqr.lsqr(A, Hm[:, b], atol=0.0, btol=0.0, maxit=25)
+        ypad = H.pack_y(inst.feat_off, facts, yo)
+        assert np.linalg.norm(Yg[:, b] - ypad) <= 1e-10 * np.linalg.norm(ypad), b
+    # to convergence with per-RHS stopping, and from a warm start
+    Y, iters, stops = rfm.rfm_lsqr_multi(plan, fact, _dev(Hm), atol=1e-12, btol=1e-12, maxit=20000)
+    D = np.stack([A.matvec(e) for e in np.eye(A.n)], axis=1)
+    kappa = np.linalg.cond(D)
+    for b in range(B):
+        ystar = H.pack_y(inst.feat_off, facts, np.linalg.lstsq(D, Hm[:, b], rcond=None)[0])
+        assert np.linalg.norm(Y.cpu().numpy()[:, b] - ystar) <= 1e-9 * kappa * np.linalg.norm(ystar)
+    assert np.all(np.isin(stops, (1, 2, 4)))
+    Y2, iters2, _ = rfm.rfm_lsqr_multi(plan, fact, _dev(Hm), Y0=Y.clone(), atol=1e-10, btol=1e-10, maxit=20000)
+    assert np.all(iters2 <= 2)
