@@ -234,6 +234,8 @@ typedef struct {
   int64_t polish;         /* precision form: binary64 LSQR iterations of the finish (included
                              in iters)                                      */
   int32_t stop;           /* 1: S1, 2: S2, 3: maxit, 4: breakdown (exact solution) */
+  int32_t warm_rejected;  /* 1: the warm start y0 was discarded (||h - A y0|| > ||h||) and the
+                             solve started from 0 */
   double rnorm_est;       /* ||r|| estimate at the stop                      */
   double artnorm_est;     /* ||A^T r|| estimate at the stop                  */
   double anorm;           /* ||A|| used by the rule: sqrt(sum_j r_j)         */
@@ -262,7 +264,8 @@ size_t rfm_lsqr_ws_bytes(const rfm_layout *L);
  * least-squares systems (non-zero optimal residual) leaves ||A^T r|| near u_low ||A|| ||r||;
  * the finish removes that bias.  opts->maxit caps all iterations together.
  * Vectors: h device [N]; y0, y device [ncols] (entry (j,k) for k < r_j at feat_off[j]+k
- * in pivot order; other entries of y are set to 0).  (sync): returns after the solve;
+ * in pivot order; other entries of y are set to 0).  A warm start whose residual
+ * ||h - A y0|| exceeds ||h|| is discarded and the solve starts from 0 (info->warm_rejected).  (sync): returns after the solve;
  * RFM_ENOTCONV if maxit was reached. */
 rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A, const double *h,
                           const double *y0, const rfm_lsqr_opts *opts, double *y,
@@ -323,6 +326,33 @@ rfm_status rfm_adam_step(int64_t n, float *p, const float *g, float *m, float *v
 /* out[i, :] = in[idx[i], :] for row-major [* x cols] binary32 matrices (mini-batch gather). */
 rfm_status rfm_gather_rows(int32_t rows, int32_t cols, const int32_t *idx, const float *in,
                            float *out, void *stream);
+
+/* Learned form, data and training.
+ * rfm_weighted_rhs: H[r, b] = weight[r] rhs[r, b] for nrhs right-hand sides (row scaling of
+ *   eq. ELMFBPINN_ls), device [N x nrhs] right-hand-side-minor.
+ * rfm_solutions_to_rows: out[row0 + b, k] = (float) Y[k, b]: nrhs LSQR solutions (device
+ *   [ncols x nrhs]) as rows of a binary32 target matrix [* x ncols].
+ * rfm_standardize_columns: per-column mean and standard deviation over n rows (sd = 1 for a
+ *   constant column), then T <- (T - mean) / sd in place; mean, sd device [cols].
+ * rfm_decode_start: y0[k, b] = pred[b, k] sd[k] + mean[k] on kept coordinates, 0 elsewhere
+ *   (network predictions [nrhs x ncols] to binary64 LSQR starts [ncols x nrhs]).
+ * rfm_mlp_train (sync): `epochs` passes of mini-batch Adam (lr, 0.9, 0.999, 1e-8) over the n
+ *   rows of X [n x n_in] and T [n x n_out]; the sample order is reshuffled every epoch
+ *   (splitmix64 from `seed`, Fisher-Yates) into idx (device [n]); G, Mom, Var are gradient and
+ *   moment buffers shaped like P (Mom, Var zeroed by the caller); scratch holds at least
+ *   batch (n_in + 3 n_out + 4 n_hidden) + 65 floats; ws rfm_mlp_ws_bytes(P, batch) bytes;
+ *   loss_history (host, nullable, [epochs]) the mean batch loss per epoch. */
+rfm_status rfm_weighted_rhs(int64_t N, int32_t nrhs, const double *weight, const double *rhs, double *H,
+                            void *stream);
+rfm_status rfm_solutions_to_rows(int64_t ncols, int32_t nrhs, const double *Y, int64_t row0, float *out,
+                                 void *stream);
+rfm_status rfm_standardize_columns(int64_t n, int64_t cols, float *T, float *mean, float *sd, void *stream);
+rfm_status rfm_decode_start(const rfm_layout *L, const int32_t *rank, int32_t nrhs, const float *pred,
+                            const float *mean, const float *sd, double *y0, void *stream);
+rfm_status rfm_mlp_train(const rfm_mlp *P, const rfm_mlp *G, const rfm_mlp *Mom, const rfm_mlp *Var,
+                         const float *X, const float *T, int64_t n, int32_t batch, int32_t epochs, float lr,
+                         uint64_t seed, int32_t *idx, float *scratch, size_t scratch_floats, void *ws,
+                         size_t ws_bytes, float *loss_history, void *stream);
 
 /* Autotuner of the batching form (sync).  Times, with HIP events on `stream`, every
  * candidate launch shape of the filter on the caller's data (rrqr_threads in {256, 512,

@@ -732,9 +732,11 @@ struct Graph {
 
 // LSQR with the launcher's operator on the right-hand side X.h, from y0 (nullable) into y.
 // Fills *out with the final scalar state (iterations, stop reason, estimates).
+// A warm start whose residual ||h - A y0|| exceeds ||h|| is discarded for the cold start
+// (the cold start stays the fallback); *rejected (nullable) reports it.
 rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, double atol, double btol,
                     int64_t maxit, int check_every, bool use_graph, rfm_kernel_times *times,
-                    double *history, hipStream_t st, State *out) {
+                    double *history, hipStream_t st, State *out, int32_t *rejected = nullptr) {
   const rfm_layout *L = X.L;
   State hs{};
   hs.anorm = anorm;
@@ -750,13 +752,26 @@ rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, doub
   RFM_LAUNCH_CHECK();
 
   // r0 = h - A y0, beta_1 u_1 = r0, alpha_1 v_1 = A^T u_1, w_1 = v_1
-  if (y0) {
+  bool cold = (y0 == nullptr);
+  if (rejected) *rejected = 0;
+  if (!cold) {
     X.fwd(st, y, X.W.st, RESID);
     X.gather(st, nullptr, X.W.p[0], X.W.st, RESID);
-  } else {
-    X.gather(st, nullptr, X.W.p[0], X.W.st, COPYH);
+    X.reduce(st, X.g_rows(), X.W.st, R_BETA_INIT);
+    RFM_LAUNCH_CHECK();
+    RFM_HIP_TRY(hipMemcpyAsync(&hs, X.W.st, sizeof(State), hipMemcpyDeviceToHost, st));
+    RFM_HIP_TRY(hipStreamSynchronize(st));
+    if (hs.beta_next > hs.hnorm) {
+      cold = true;
+      if (rejected) *rejected = 1;
+      hipLaunchKernelGGL(init_y, dim3(ceil_div(L->max_cols > 0 ? L->max_cols : 1, 256), L->J), dim3(256), 0, st, *L,
+                         X.A->rank, (const double *)nullptr, y);
+    }
   }
-  X.reduce(st, X.g_rows(), X.W.st, R_BETA_INIT);
+  if (cold) {
+    X.gather(st, nullptr, X.W.p[0], X.W.st, COPYH);
+    X.reduce(st, X.g_rows(), X.W.st, R_BETA_INIT);
+  }
   X.adj(st, X.W.p[0], nullptr, X.W.q[0], X.W.st, INIT);
   X.reduce(st, X.n_adj_part(), X.W.st, R_ALPHA_INIT);
   X.yw(st, X.W.q[0], y, X.W.st, INIT);
@@ -901,9 +916,10 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   State hs{}, hc{};
   int64_t outer = 0;
   info->polish = 0;
+  info->warm_rejected = 0;
   if (!mixed) {
     rfm_status s = run_lsqr(X, anorm, y0, y, opts->atol, opts->btol, opts->maxit, opts->check_every,
-                            opts->use_graph != 0, opts->times, opts->history, st, &hs);
+                            opts->use_graph != 0, opts->times, opts->history, st, &hs, &info->warm_rejected);
     if (s != RFM_OK) return s;
     s = explicit_check(X, y, st, &hc);
     if (s != RFM_OK) return s;

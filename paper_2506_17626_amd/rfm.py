@@ -73,7 +73,7 @@ class LsqrOpts(C.Structure):
 
 class LsqrInfo(C.Structure):
     _fields_ = [("iters", C.c_int64), ("outer", C.c_int64), ("polish", C.c_int64), ("stop", C.c_int32),
-                ("rnorm_est", C.c_double),
+                ("warm_rejected", C.c_int32), ("rnorm_est", C.c_double),
                 ("artnorm_est", C.c_double), ("anorm", C.c_double), ("hnorm", C.c_double),
                 ("ynorm", C.c_double), ("relres", C.c_double), ("eta", C.c_double)]
 
@@ -401,3 +401,71 @@ def rfm_lsqr_multi(plan: Plan, fact: dict, H, Y0=None, atol=1e-8, btol=1e-8, max
                                _np_ptr(iters), _np_ptr(stops), _ptr(ws), nb, _stream()), "rfm_lsqr_multi",
            allow=(RFM_ENOTCONV,))
     return Y, iters, stops
+
+
+# ---------------------------------------------------------------- learned form: data and training
+_lib.rfm_weighted_rhs.restype = C.c_int
+_lib.rfm_weighted_rhs.argtypes = [C.c_int64, C.c_int32, _p, _p, _p, _p]
+_lib.rfm_solutions_to_rows.restype = C.c_int
+_lib.rfm_solutions_to_rows.argtypes = [C.c_int64, C.c_int32, _p, C.c_int64, _p, _p]
+_lib.rfm_standardize_columns.restype = C.c_int
+_lib.rfm_standardize_columns.argtypes = [C.c_int64, C.c_int64, _p, _p, _p, _p]
+_lib.rfm_decode_start.restype = C.c_int
+_lib.rfm_decode_start.argtypes = [C.POINTER(Layout), _p, C.c_int32, _p, _p, _p, _p, _p]
+_lib.rfm_mlp_train.restype = C.c_int
+_lib.rfm_mlp_train.argtypes = [C.POINTER(Mlp), C.POINTER(Mlp), C.POINTER(Mlp), C.POINTER(Mlp), _p, _p, C.c_int64,
+                               C.c_int32, C.c_int32, C.c_float, C.c_uint64, _p, _p, C.c_size_t, _p, C.c_size_t, _p, _p]
+EXPORTED += ["rfm_weighted_rhs", "rfm_solutions_to_rows", "rfm_standardize_columns", "rfm_decode_start",
+             "rfm_mlp_train"]
+
+
+def rfm_weighted_rhs(weight, rhs_nb):
+    """rhs_nb: [N, nrhs] binary64 -> H [N, nrhs] scaled by the row weights."""
+    H = torch.empty_like(rhs_nb)
+    _check(_lib.rfm_weighted_rhs(rhs_nb.shape[0], rhs_nb.shape[1], _ptr(weight), _ptr(rhs_nb), _ptr(H), _stream()),
+           "rfm_weighted_rhs")
+    return H
+
+
+def rfm_solutions_to_rows(Y, row0, out):
+    _check(_lib.rfm_solutions_to_rows(Y.shape[0], Y.shape[1], _ptr(Y), row0, _ptr(out), _stream()),
+           "rfm_solutions_to_rows")
+    return out
+
+
+def rfm_standardize_columns(T):
+    mean = torch.empty(T.shape[1], dtype=torch.float32, device=T.device)
+    sd = torch.empty_like(mean)
+    _check(_lib.rfm_standardize_columns(T.shape[0], T.shape[1], _ptr(T), _ptr(mean), _ptr(sd), _stream()),
+           "rfm_standardize_columns")
+    return mean, sd
+
+
+def rfm_decode_start(plan: Plan, fact: dict, pred, mean, sd):
+    """pred [nrhs, ncols] binary32 -> starts [ncols, nrhs] binary64 (a vector for nrhs = 1)."""
+    L = plan.layout
+    B = pred.shape[0]
+    y0 = torch.empty(L.ncols, B, dtype=torch.float64, device=pred.device)
+    _check(_lib.rfm_decode_start(C.byref(L), _ptr(fact["rank"]), B, _ptr(pred), _ptr(mean), _ptr(sd), _ptr(y0),
+                                 _stream()), "rfm_decode_start")
+    return y0[:, 0].contiguous() if B == 1 else y0
+
+
+def rfm_mlp_train(P: dict, X, T, epochs, batch=256, lr=1e-3, seed=0):
+    """Mini-batch Adam on the device; P is updated in place.  Returns the per-epoch mean loss."""
+    S = mlp_struct(P)
+    dev = X.device
+    G = {k: torch.zeros_like(v) for k, v in P.items()}
+    Mo = {k: torch.zeros_like(v) for k, v in P.items()}
+    Va = {k: torch.zeros_like(v) for k, v in P.items()}
+    n = X.shape[0]
+    nsc = batch * (S.n_in + 3 * S.n_out + 4 * S.n_hidden) + 65
+    scratch = torch.empty(nsc, dtype=torch.float32, device=dev)
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    nb = _lib.rfm_mlp_ws_bytes(C.byref(S), batch)
+    ws = _ws(nb, dev)
+    hist = np.zeros(epochs, dtype=np.float32)
+    _check(_lib.rfm_mlp_train(C.byref(S), C.byref(mlp_struct(G)), C.byref(mlp_struct(Mo)), C.byref(mlp_struct(Va)),
+                              _ptr(X), _ptr(T), n, batch, epochs, lr, seed, _ptr(idx), _ptr(scratch), nsc, _ptr(ws),
+                              nb, _np_ptr(hist), _stream()), "rfm_mlp_train")
+    return hist
