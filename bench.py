@@ -103,6 +103,84 @@ def cpu_baseline(inst, tau, nblocks):
                       f"{inst.J} blocks, one thread, {dt:.1f} s"}
 
 
+def learned_study(args):
+    """Learned warm start on the parametric Poisson family (2D geometry, 16x16 subdomains, 256
+    features): training solves by multi-RHS LSQR (capped), perceptron trained on the device,
+    then held-out members solved cold and warm (multi-RHS, to the 1e-8 rule), and a few single
+    solves timed plain FP64 cold, FP64 warm, and FP32-refined warm."""
+    import torch
+
+    from paper_2506_17626_amd import instances as I
+    from paper_2506_17626_amd import learned, rfm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    inst = I.workload("poisson2d_family", seed=args.seed)
+    plan = rfm.plan_instance(inst)
+    prob = rfm.problem_tensors(inst)
+    M, h = rfm.rfm_assemble(plan, prob)
+    fact = rfm.rfm_rrqr_filter(plan, M, args.tau)
+    fact["Qlow"] = rfm.rfm_pack_q(plan, fact, rfm.F32)
+    train = I.poisson2d_family_params(args.n_train, seed=1000 + args.seed)
+    test = I.poisson2d_family_params(args.n_test, seed=2000 + args.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    def note(msg):
+        print(f"[learned study] {msg}", file=sys.stderr, flush=True)
+
+    note(f"factored: {int(fact['rank'].sum())} kept columns; solving {args.n_train} training members")
+    ts = learned.solve_members(plan, fact, inst, prob, train, 30, tol=args.tol, maxit=args.train_iters,
+                               progress=lambda d, n: note(f"training solves {d}/{n}"))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    model = learned.train_warm_start(ts, hidden=512, epochs=args.epochs, batch=256, lr=1e-3, seed=args.seed)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    note(f"trained {args.epochs} epochs, loss {model.loss_history[0]:.3e} -> {model.loss_history[-1]:.3e}")
+    Ht = learned.family_rhs(inst, prob, test)
+    Y0 = model.starts(plan, fact, test)
+    Yc, ic, sc = rfm.rfm_lsqr_multi(plan, fact, Ht, atol=args.tol, btol=args.tol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    note(f"held-out cold solves done, mean {np.mean(ic):.0f} iterations")
+    rej = np.zeros(Ht.shape[1], dtype=np.int32)
+    Yw, iw, sw = rfm.rfm_lsqr_multi(plan, fact, Ht, Y0=Y0, atol=args.tol, btol=args.tol, maxit=args.maxit,
+                                    rejected=rej)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    start_err = (torch.linalg.norm(Y0 - Yc, dim=0) / torch.linalg.norm(Yc, dim=0)).cpu().numpy()
+    sol_diff = (torch.linalg.norm(Yw - Yc, dim=0) / torch.linalg.norm(Yc, dim=0)).cpu().numpy()
+    singles = []
+    for b in range(min(args.n_single, len(test))):
+        hb = Ht[:, b].contiguous()
+        y0 = Y0[:, b].contiguous()
+        row = {}
+        for name, kw in (("plain_fp64_cold", {}), ("plain_fp64_warm", {"y0": y0}),
+                         ("mixed_f32_warm", {"y0": y0, "inner_dtype": rfm.F32, "inner_tol": 1e-4})):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            _, info = rfm.rfm_lsqr_solve(plan, fact, hb, atol=args.tol, btol=args.tol, maxit=args.maxit,
+                                         check_every=64, use_graph=1, **kw)
+            torch.cuda.synchronize()
+            row[name] = {"ms": 1e3 * (time.perf_counter() - ta), "iters": int(info.iters), "stop": int(info.stop),
+                         "relres": info.relres, "warm_rejected": int(info.warm_rejected)}
+            note(f"single solve {b} {name}: {row[name]['ms']:.0f} ms, {row[name]['iters']} iterations")
+        singles.append(row)
+    out = {
+        "study": "learned warm start", "workload": "parametric 2D Poisson family, 16x16 subdomains, 256 features",
+        "tau": args.tau, "tol": args.tol, "n_train": args.n_train, "train_iters_cap": args.train_iters,
+        "train_solve_s": t1 - t0, "train_stops": np.bincount(ts.stops, minlength=5).tolist(),
+        "train_s": t2 - t1, "epochs": args.epochs, "loss_first": float(model.loss_history[0]),
+        "loss_last": float(model.loss_history[-1]), "n_test": args.n_test, "heldout_solve_s": t3 - t2,
+        "heldout_iters_cold_mean": float(np.mean(ic)), "heldout_iters_warm_mean": float(np.mean(iw)),
+        "heldout_iters_cold": ic.tolist(), "heldout_iters_warm": iw.tolist(),
+        "heldout_stops_cold": np.bincount(sc, minlength=5).tolist(),
+        "heldout_stops_warm": np.bincount(sw, minlength=5).tolist(), "heldout_starts_rejected": int(rej.sum()),
+        "start_rel_err_mean": float(np.mean(start_err)), "warm_vs_cold_solution_rel_diff_max": float(sol_diff.max()),
+        "single_solves": singles,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +198,17 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (a device copy of known "
                          "size, used to calibrate the HBM byte counters of a profiler run)")
+    ap.add_argument("--learned-study", action="store_true",
+                    help="run the learned warm-start study on the parametric family instead of the bench")
+    ap.add_argument("--n-train", type=int, default=1024)
+    ap.add_argument("--n-test", type=int, default=64)
+    ap.add_argument("--n-single", type=int, default=2)
+    ap.add_argument("--train-iters", type=int, default=4000)
+    ap.add_argument("--epochs", type=int, default=200)
     args = ap.parse_args()
+    if args.learned_study:
+        learned_study(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the kernels are measured on one GPU's share of the "
               "subdomains; the multi-GPU layout is described, not built.", file=sys.stderr)
@@ -224,11 +312,23 @@ def main():
         "lsqr": {"plain_fp64_ms": phase_ms["lsqr"], "iters": iters, "stop": int(info.stop),
                  "us_per_iter": 1e3 * phase_ms["lsqr"] / max(iters, 1),
                  "relres": info.relres, "eta": info.eta, "tol": args.tol,
-                 "mixed_warm_ms": None},
+                 "mixed_warm_ms": None},   # the learned start belongs to the parametric family (--learned-study)
         "phase_ms": phase_ms, "lsqr_stages": kern, "dominant_ms_per_step": per_step,
         "kept_columns": int(ranks.sum()),
         "roofline": roof,
     }
+    # precision form on the same system: one solve after the timed steps
+    fact["Qlow"] = rfm.rfm_pack_q(plan, fact, rfm.F32)
+    ea, eb = E(), E()
+    ea.record()
+    _, minfo = rfm.rfm_lsqr_solve(plan, fact, h, atol=args.tol, btol=args.tol, maxit=args.maxit,
+                                  check_every=args.check_every, use_graph=0 if args.no_graph else 1, y=y, ws=ws,
+                                  inner_dtype=rfm.F32, inner_tol=1e-4)
+    eb.record()
+    torch.cuda.synchronize()
+    out["lsqr"]["mixed_f32_ms"] = ea.elapsed_time(eb)
+    out["lsqr"]["mixed_f32"] = {"iters": int(minfo.iters), "outer": int(minfo.outer), "finish": int(minfo.polish),
+                                "stop": int(minfo.stop), "relres": minfo.relres, "eta": minfo.eta}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, args.tau, args.cpu_blocks)
     if args.copy_probe_mib > 0:

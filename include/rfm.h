@@ -280,10 +280,13 @@ size_t rfm_lsqr_multi_ws_bytes(const rfm_layout *L, int32_t nrhs);
  * block products are dense matrix-matrix products.  Right-hand-side-minor layout: H device
  * [N x nrhs], Y0 (nullable) and Y device [ncols x nrhs] (entry (j,k) of right-hand side b at
  * (feat_off[j] + k) * nrhs + b).  A finished right-hand side is frozen while the others go on.
- * iters, stops: host [nrhs], nullable.  RFM_ENOTCONV if any right-hand side reached maxit. */
+ * With Y0, each right-hand side's start passes the guard of rfm_lsqr_solve: one whose residual
+ * ||h_b - A y0_b|| exceeds ||h_b|| is replaced by the zero start.
+ * iters, stops, rejected (1 where the guard dropped the start): host [nrhs], nullable.
+ * RFM_ENOTCONV if any right-hand side reached maxit. */
 rfm_status rfm_lsqr_multi(const rfm_layout *L, const rfm_operator *A, const double *H, int32_t nrhs,
                           const double *Y0, const rfm_lsqr_opts *opts, double *Y, int64_t *iters,
-                          int32_t *stops, void *ws, size_t ws_bytes, void *stream);
+                          int32_t *stops, int32_t *rejected, void *ws, size_t ws_bytes, void *stream);
 
 /* Back-substitution a_hat_j = R_hat_j^{-1} y_j and scatter to the global coefficient
  * vector with zeros at dropped columns (Algorithm 2, output step).

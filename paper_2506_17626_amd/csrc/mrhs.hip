@@ -349,6 +349,12 @@ __global__ void mr_init_y(rfm_layout L, const int32_t *rank, const double *Y0, d
   Y[(f0 + k) * B + b] = (Y0 && k < rank[j]) ? Y0[(f0 + k) * B + b] : 0.0;
 }
 
+// zero the columns b of Y whose bit is set in mask (starts discarded by the warm-start guard)
+__global__ void mr_drop_start(int64_t ncols, int B, uint64_t mask, double *Y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ncols * B && ((mask >> (e % B)) & 1ull)) Y[e] = 0.0;
+}
+
 __global__ void mr_zero(double *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -399,7 +405,7 @@ extern "C" size_t rfm_lsqr_multi_ws_bytes(const rfm_layout *L, int32_t nrhs) {
 
 extern "C" rfm_status rfm_lsqr_multi(const rfm_layout *L, const rfm_operator *A, const double *H, int32_t nrhs,
                                      const double *Y0, const rfm_lsqr_opts *opts, double *Y, int64_t *iters,
-                                     int32_t *stops, void *ws, size_t ws_bytes, void *stream) {
+                                     int32_t *stops, int32_t *rejected, void *ws, size_t ws_bytes, void *stream) {
   using namespace rfm;
   rfm_status s0 = check_layout(L, "rfm_lsqr_multi");
   if (s0 != RFM_OK) return s0;
@@ -430,16 +436,39 @@ extern "C" rfm_status rfm_lsqr_multi(const rfm_layout *L, const rfm_operator *A,
   hipLaunchKernelGGL(mr_init_y, dim3(ceil_div((int64_t)(L->max_cols > 0 ? L->max_cols : 1) * B, 256), L->J), dim3(256),
                      0, st, *L, A->rank, Y0, Y, B);
   // r0 = H - A Y0 (or H), beta u = r0, alpha v = A^T u, w = v
-  if (Y0) {
+  auto residual = [&]() {
     hipLaunchKernelGGL(mr_fwd, g_fwd, dim3(256), 0, st, *L, A->Q, A->rank, Y, W.t, B, W.st, (int)M_RESID);
     hipLaunchKernelGGL(mr_gather, dim3(g_rows), dim3(256), 0, st, *L, W.t, H, (const double *)nullptr, W.p[0], B,
                        W.part, W.part2, W.st, (int)M_RESID);
+    hipLaunchKernelGGL(mr_reduce, dim3(B), dim3(256), 0, st, W.part, W.part2, (int64_t)g_rows, B, W.st, gl,
+                       (int)MR_BETA_INIT);
+  };
+  std::vector<MState> hs(B);
+  if (rejected)
+    for (int b = 0; b < B; ++b) rejected[b] = 0;
+  if (Y0) {
+    // warm-start guard, per right-hand side: a start whose residual exceeds ||h_b|| is replaced
+    // by the zero start (the rule of rfm_lsqr_solve)
+    residual();
+    RFM_LAUNCH_CHECK();
+    RFM_HIP_TRY(hipMemcpyAsync(hs.data(), W.st, sizeof(MState) * B, hipMemcpyDeviceToHost, st));
+    RFM_HIP_TRY(hipStreamSynchronize(st));
+    uint64_t mask = 0;
+    for (int b = 0; b < B; ++b)
+      if (hs[b].beta_next > hs[b].hnorm) {
+        mask |= 1ull << b;
+        if (rejected) rejected[b] = 1;
+      }
+    if (mask) {
+      hipLaunchKernelGGL(mr_drop_start, dim3(ceil_div(nvec, 256)), dim3(256), 0, st, L->ncols, B, mask, Y);
+      residual();
+    }
   } else {
     hipLaunchKernelGGL(mr_gather, dim3(g_rows), dim3(256), 0, st, *L, W.t, H, (const double *)nullptr, W.p[0], B,
                        W.part, W.part2, W.st, (int)M_COPYH);
+    hipLaunchKernelGGL(mr_reduce, dim3(B), dim3(256), 0, st, W.part, W.part2, (int64_t)g_rows, B, W.st, gl,
+                       (int)MR_BETA_INIT);
   }
-  hipLaunchKernelGGL(mr_reduce, dim3(B), dim3(256), 0, st, W.part, W.part2, (int64_t)g_rows, B, W.st, gl,
-                     (int)MR_BETA_INIT);
   hipLaunchKernelGGL(mr_adj, g_adj, dim3(256), 0, st, *L, A->Q, A->rank, W.p[0], (const double *)nullptr, W.q[0], B,
                      W.part, W.st, (int)M_INIT);
   hipLaunchKernelGGL(mr_reduce, dim3(B), dim3(256), 0, st, W.part, W.part2, n_adj, B, W.st, gl, (int)MR_ALPHA_INIT);
@@ -447,7 +476,6 @@ extern "C" rfm_status rfm_lsqr_multi(const rfm_layout *L, const rfm_operator *A,
   hipLaunchKernelGGL(mr_reduce, dim3(B), dim3(256), 0, st, W.part, W.part2, (int64_t)g_cols, B, W.st, gl,
                      (int)MR_Y_INIT);
   RFM_LAUNCH_CHECK();
-  std::vector<MState> hs(B);
   int64_t i = 0;
   for (;;) {
     RFM_HIP_TRY(hipMemcpyAsync(hs.data(), W.st, sizeof(MState) * B, hipMemcpyDeviceToHost, st));

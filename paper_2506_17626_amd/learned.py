@@ -41,8 +41,9 @@ class TrainingSet:
     stops: np.ndarray
 
 
-def solve_members(plan, fact, inst, prob, params, maxfreq, tol=1e-8, maxit=20000, group=64):
-    """Solve every member with multi-RHS LSQR; targets as binary32 rows."""
+def solve_members(plan, fact, inst, prob, params, maxfreq, tol=1e-8, maxit=20000, group=64, progress=None):
+    """Solve every member with multi-RHS LSQR; targets as binary32 rows.  ``progress`` (nullable)
+    is called with (members done, members) after every group."""
     L = plan.layout
     dev = prob["weight"].device
     n = params.shape[0]
@@ -57,6 +58,8 @@ def solve_members(plan, fact, inst, prob, params, maxfreq, tol=1e-8, maxit=20000
         rfm.rfm_solutions_to_rows(Y, g0, T)
         iters[g0:g0 + len(chunk)] = it
         stops[g0:g0 + len(chunk)] = sp
+        if progress is not None:
+            progress(g0 + len(chunk), n)
     X = torch.from_numpy(encode(params, maxfreq)).to(dev)
     return TrainingSet(X, T, iters, stops)
 

@@ -135,7 +135,7 @@ def _ptr(t):
 
 
 def _np_ptr(a):
-    return a.ctypes.data_as(C.c_void_p)
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
 def _stream():
@@ -378,13 +378,14 @@ _lib.rfm_lsqr_multi_ws_bytes.restype = C.c_size_t
 _lib.rfm_lsqr_multi_ws_bytes.argtypes = [C.POINTER(Layout), C.c_int32]
 _lib.rfm_lsqr_multi.restype = C.c_int
 _lib.rfm_lsqr_multi.argtypes = [C.POINTER(Layout), C.POINTER(Operator), _p, C.c_int32, _p, C.POINTER(LsqrOpts), _p,
-                                _p, _p, _p, C.c_size_t, _p]
+                                _p, _p, _p, _p, C.c_size_t, _p]
 EXPORTED += ["rfm_lsqr_multi_ws_bytes", "rfm_lsqr_multi"]
 
 
 def rfm_lsqr_multi(plan: Plan, fact: dict, H, Y0=None, atol=1e-8, btol=1e-8, maxit=10000, check_every=64,
-                   Y=None, ws=None):
-    """H: [N, nrhs] binary64 (right-hand-side-minor); returns Y [ncols, nrhs], iters, stops."""
+                   Y=None, ws=None, rejected=None):
+    """H: [N, nrhs] binary64 (right-hand-side-minor); returns Y [ncols, nrhs], iters, stops.
+    ``rejected`` (optional int32 numpy array [nrhs]) receives the warm-start guard's flags."""
     L = plan.layout
     B = H.shape[1]
     dev = H.device
@@ -398,7 +399,8 @@ def rfm_lsqr_multi(plan: Plan, fact: dict, H, Y0=None, atol=1e-8, btol=1e-8, max
     iters = np.zeros(B, dtype=np.int64)
     stops = np.zeros(B, dtype=np.int32)
     _check(_lib.rfm_lsqr_multi(C.byref(L), C.byref(op), _ptr(H), B, _ptr(Y0), C.byref(opts), _ptr(Y),
-                               _np_ptr(iters), _np_ptr(stops), _ptr(ws), nb, _stream()), "rfm_lsqr_multi",
+                               _np_ptr(iters), _np_ptr(stops), _np_ptr(rejected), _ptr(ws), nb, _stream()),
+           "rfm_lsqr_multi",
            allow=(RFM_ENOTCONV,))
     return Y, iters, stops
 

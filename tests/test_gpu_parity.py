@@ -492,3 +492,24 @@ def test_lsqr_multi_rhs_matches_oracle_per_rhs(rfm):
     assert np.all(np.isin(stops, (1, 2, 4)))
     Y2, iters2, _ = rfm.rfm_lsqr_multi(plan, fact, _dev(Hm), Y0=Y.clone(), atol=1e-10, btol=1e-10, maxit=20000)
     assert np.all(iters2 <= 2)
+
+
+def test_multi_rhs_warm_start_guard_per_column(rfm):
+    """A harmful start in some columns is dropped for those columns only: they then run the
+    cold recurrence bit for bit, while the good starts are kept."""
+    inst = I.tiny("poisson2d")
+    rows, blocks, h, facts, plan, fact = _shared_fact(rfm, inst, 1e-8)
+    rng = np.random.default_rng(9)
+    B = 4
+    Hm = _dev(np.stack([h * rng.uniform(0.5, 2.0) + 0.1 * rng.standard_normal(inst.N) for _ in range(B)], axis=1))
+    Yc, ic, _ = rfm.rfm_lsqr_multi(plan, fact, Hm, atol=1e-10, btol=1e-10, maxit=20000)
+    Y0 = Yc.clone()
+    Y0[:, 1] = 1e6
+    Y0[:, 3] = -1e6
+    rej = np.full(B, -1, dtype=np.int32)
+    Yw, iw, sw = rfm.rfm_lsqr_multi(plan, fact, Hm, Y0=Y0, atol=1e-10, btol=1e-10, maxit=20000, rejected=rej)
+    assert rej.tolist() == [0, 1, 0, 1]
+    for b in (1, 3):
+        assert iw[b] == ic[b] and torch.equal(Yw[:, b], Yc[:, b])
+    for b in (0, 2):
+        assert iw[b] <= 2
