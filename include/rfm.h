@@ -131,19 +131,26 @@ size_t rfm_rrqr_ws_bytes(const rfm_layout *L);
 
 /* sigma-RRQR filter of every block (Algorithm 1), one workgroup per block:
  * column-pivoted Householder QR (at each step the column with the largest norm
- * orthogonal to the columns already chosen; bit-equal norms go to the smallest
- * local feature id), stopping at the first step s with |R_ss| <= tau * |R_00|
- * (threshold relative to the leading diagonal of R_j).  tau in [0, 1).
+ * orthogonal to the columns already chosen, the norms recomputed exactly from the updated
+ * columns; bit-equal norms go to the smallest local feature id), stopping at the first
+ * step s with |R_ss| <= tau * |R_00| (threshold relative to the leading diagonal of R_j).
+ * tau in [0, 1).  By default (max_cols <= 512) the pivoted factorisation runs on the
+ * triangular factor R0 of an unpivoted QR M_j = Q0 R0, which has the same pivots, R and
+ * Q = Q0 Q1 in exact arithmetic (R-first form); rfm_rrqr_filter_tuned can select the direct
+ * factorisation of M_j.  The two give the same factors up to rounding.
  * Inputs:  M device [nnz] (not modified).
  * Outputs: rank device [J]        r_j (0 <= r_j <= min(|I_j|, K_j));
  *          kept device [ncols]    kept local feature ids in pivot order, entries
  *                                 k < r_j of block j used, the rest set to -1;
  *          R    device [nrsq]     upper-triangular R_hat_j (r_j x r_j, positive
- *                                 diagonal, in the block's K_j x K_j slot);
+ *                                 diagonal, in the block's K_j x K_j slot; the R-first
+ *                                 form also sets the rest of the slot to zero);
  *          Q    device [nnz]      explicit Q_hat_j (first r_j columns of the block's
  *                                 slot, orthonormal, Q_hat_j R_hat_j = M_j[:, kept]);
  *          ratios device [ncols]  nullable; |R_ss|/|R_00| for every step taken, the
  *                                 stopping step included, 0 elsewhere.
+ * ws: device workspace of rfm_rrqr_ws_bytes(L) bytes (needed by the R-first form and the
+ * persistent launch; contents on return unspecified).
  * Sizes: max_rows <= 3072 and max_cols <= 2048 (RFM_EUNSUPPORTED otherwise). */
 rfm_status rfm_rrqr_filter(const rfm_layout *L, const double *M, double tau, int32_t *rank,
                            int32_t *kept, double *R, double *Q, double *ratios, void *ws,
@@ -154,11 +161,19 @@ typedef struct {
   int32_t rrqr_threads;    /* workgroup size of the filter: 256, 512 or 1024 (1024 only for
                               blocks of at most 1024 rows); 0 = by block height */
   int32_t rrqr_persistent; /* 1: one persistent launch whose workgroups take blocks from a
-                              shared counter in the given order (largest first) */
+                              shared counter in the given order (largest first); a form
+                              of the direct factorisation (RFM_RRQR_AUTO then takes it) */
   int32_t rrqr_wgs_per_cu; /* persistent grid = rrqr_wgs_per_cu x CUs (>= 1)  */
   int32_t adj_tile;        /* columns per workgroup of the adjoint block products of LSQR
                               (a multiple of 16; 0 = about 4096 workgroups in all) */
+  int32_t rrqr_algo;       /* rfm_rrqr_algo: the filter's factorisation */
 } rfm_tuning;
+
+typedef enum {
+  RFM_RRQR_AUTO = 0,   /* R-first when max_cols <= 512, else direct */
+  RFM_RRQR_DIRECT = 1, /* pivoted QR of M_j itself (rrqr_threads applies) */
+  RFM_RRQR_RFIRST = 2  /* pivoted QR of R0 from an unpivoted QR of M_j */
+} rfm_rrqr_algo;
 
 /* Cost order of the blocks (sync, host only): block ids sorted by decreasing Householder QR
  * flops 4mnk - 2(m+n)k^2 + 4/3 k^3, k = min(m, n), ties in id order.  row_off, feat_off
@@ -358,11 +373,12 @@ rfm_status rfm_mlp_train(const rfm_mlp *P, const rfm_mlp *G, const rfm_mlp *Mom,
                          size_t ws_bytes, float *loss_history, void *stream);
 
 /* Autotuner of the batching form (sync).  Times, with HIP events on `stream`, every
- * candidate launch shape of the filter on the caller's data (rrqr_threads in {256, 512,
- * 1024}, default and persistent launches with 1 or 2 workgroups per CU) and then the
- * adjoint tile of LSQR (adj_tile in {16, 32, 64, 128, 256}) over a short solve of
- * lsqr_iters iterations on h, and writes the fastest shapes to *best.  The filter outputs
- * (rank, kept, R, Q, ratios) hold the result of the last candidate run (identical for all).
+ * candidate launch shape of the filter on the caller's data (the R-first form when
+ * max_cols <= 512, and the direct form with rrqr_threads in {256, 512, 1024} as default
+ * and persistent launches with 1 or 2 workgroups per CU) and then the adjoint tile
+ * of LSQR (adj_tile in {16, 32, 64, 128, 256}) over a short solve of lsqr_iters iterations
+ * on h, and writes the fastest shapes to *best.  The filter outputs (rank, kept, R, Q,
+ * ratios) hold the result of the winning filter shape.
  * ms_out / cand_out (host, nullable, capacity 32) receive every candidate's time and shape;
  * *ncand their number.  ws: max(rfm_rrqr_ws_bytes, rfm_lsqr_ws_bytes) bytes of device memory;
  * y_scratch: device [ncols]. */

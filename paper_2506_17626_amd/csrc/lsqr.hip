@@ -933,6 +933,16 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
     hipLaunchKernelGGL(init_y, dim3(ceil_div(L->max_cols > 0 ? L->max_cols : 1, 256), L->J), dim3(256), 0, st,
                        *L, A->rank, y0, y);
     RFM_LAUNCH_CHECK();
+    if (y0) {  // the warm-start guard of the plain path, on the binary64 residual
+      rfm_status s = explicit_check(X, y, st, &hc);
+      if (s != RFM_OK) return s;
+      if (hc.rnorm > hc.hnorm) {
+        info->warm_rejected = 1;
+        hipLaunchKernelGGL(init_y, dim3(ceil_div(L->max_cols > 0 ? L->max_cols : 1, 256), L->J), dim3(256), 0, st,
+                           *L, A->rank, (const double *)nullptr, y);
+        RFM_LAUNCH_CHECK();
+      }
+    }
     int64_t inner_total = 0, budget = opts->maxit;
     double prev_at = INFINITY;
     bool polish = false;

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "rrqr_rfirst.hpp"
 
 namespace rfm {
 namespace {
@@ -403,8 +404,10 @@ rfm_status validate(const rfm_layout *L, const double *M, double tau, int32_t *r
 }  // namespace rfm
 
 extern "C" size_t rfm_rrqr_ws_bytes(const rfm_layout *L) {
-  (void)L;
-  return 256;  // the work-queue counter of the persistent launch
+  // the work-queue counter of the direct form's persistent launch, or the R-first workspace
+  if (!L) return 0;
+  const size_t rf = rfm::rfirst_supported(L) ? rfm::rfirst_ws_bytes(L) : 0;
+  return rf > 256 ? rf : 256;
 }
 
 extern "C" rfm_status rfm_rrqr_filter(const rfm_layout *L, const double *M, double tau,
@@ -421,7 +424,16 @@ extern "C" rfm_status rfm_rrqr_filter_tuned(const rfm_layout *L, const double *M
   rfm_status s = validate(L, M, tau, rank, kept, R, Q, "rfm_rrqr_filter");
   if (s != RFM_OK) return s;
   const int persistent = tune ? tune->rrqr_persistent : 0;
-  if (persistent && (!ws || ws_bytes < rfm_rrqr_ws_bytes(L)))
+  const int algo = tune ? tune->rrqr_algo : RFM_RRQR_AUTO;
+  if (algo != RFM_RRQR_AUTO && algo != RFM_RRQR_DIRECT && algo != RFM_RRQR_RFIRST)
+    return fail(RFM_EINVAL, "rfm_rrqr_filter: rrqr_algo must be RFM_RRQR_AUTO, _DIRECT or _RFIRST");
+  if (algo == RFM_RRQR_RFIRST && persistent)
+    return fail(RFM_EINVAL, "rfm_rrqr_filter: the persistent launch belongs to the direct form");
+  if (algo == RFM_RRQR_RFIRST || (algo == RFM_RRQR_AUTO && !persistent && rfirst_supported(L))) {
+    RfirstArgs ra{L, M, tau, rank, kept, R, Q, ratios, order, ws, ws_bytes, (hipStream_t)stream};
+    return rrqr_rfirst(ra);
+  }
+  if (persistent && (!ws || ws_bytes < 256))
     return fail(RFM_EINVAL, "rfm_rrqr_filter: the persistent launch needs the workspace");
   const int threads = tune ? tune->rrqr_threads : 0;
   if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)

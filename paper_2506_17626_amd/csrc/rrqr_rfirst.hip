@@ -1,0 +1,957 @@
+// sigma-RRQR filter of every block (Algorithm 1), R-first form.
+//
+// The column-pivoted QR of a tall block M_j (m x n) has the same pivots, the same R and the
+// same Q (up to rounding) as the pivoted QR of the triangular factor R0 of its unpivoted QR
+// M_j = Q0 R0, because the column norms and every later step only see M_j through Q0^T M_j.
+// Working on R0 (n x n, at most 512 x 512) instead of M_j keeps the whole pivoted
+// factorisation on chip, and the two passes over the tall block need no pivoting, so
+// their updates can be deferred over panels of reflectors.  Five kernels, one workgroup
+// per block (or a persistent grid taking blocks from a counter, largest first):
+//   rf_qr     copy M_j into its Q slot; unpivoted Householder QR in panels of nb columns:
+//             the panel is factored with its columns in registers, then every trailing
+//             column is loaded once, takes the panel's nb reflectors in order, and is
+//             stored once (HBM traffic ~ 2 m n^2 / nb instead of ~ m n^2);
+//   rf_qrcp   Businger-Golub pivoting on R0 with exact norm recomputation at every step:
+//             columns live in three tiers (registers of the eight waves, LDS, then a global
+//             slot), every active column takes the step's reflector and has its norm
+//             recomputed from its updated entries; stops at the first |R_ss| <= tau |R_00|;
+//             writes R_hat (signs normalised so diag > 0) and the reflectors below it;
+//   rf_formq1 Q1 = H'_0 ... H'_{r-1} [I_r; 0] (n x r) backward, in panels;
+//   rf_formq0 Q0 = H_0 ... H_{n-1} [I_n; 0] (m x n) backward in place, in panels;
+//   rf_gemm   Q_hat = Q0 Q1 D (D the sign normalisation) in place, by row tiles in LDS.
+// Householder reflector of x (pivot row s): beta = -sign(alpha) ||x||, v = [1, x_2:/(alpha -
+// beta)], tau_h = (beta - alpha)/beta, sign(0) = +; nothing to zero gives tau_h = 0.
+#include <algorithm>
+
+#include "rrqr_rfirst.hpp"
+
+namespace rfm {
+namespace {
+
+constexpr int NT = 512;
+constexpr int NW = NT / kWave;
+constexpr size_t kLdsCap = 150 * 1024;
+
+struct Blk {
+  int m, n, nr;
+  int64_t f0, base, rsq;
+};
+
+__device__ __forceinline__ Blk blk(const rfm_layout &L, int j) {
+  Blk b;
+  b.m = (int)(L.row_off[j + 1] - L.row_off[j]);
+  b.f0 = L.feat_off[j];
+  b.n = (int)(L.feat_off[j + 1] - b.f0);
+  b.nr = b.m < b.n ? b.m : b.n;
+  b.base = L.blk_off[j];
+  b.rsq = L.rsq_off[j];
+  return b;
+}
+
+// Reflector of a column held by one wave: row r0 + lane + 64 t in x[t], rows [s, hi) live.
+// Writes v (v[0] = 1) to vdst[row - s] for rows s..hi-1 and overwrites x with beta at row s
+// and v below it (x is left as it is when there is nothing to zero).  Returns tau_h.
+template <int TT>
+__device__ __forceinline__ double reflect(double (&x)[TT], int r0, int s, int hi, double *vdst) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double alpha = 0.0, sig2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    const int row = r0 + lane + kWave * t;
+    if (row == s) alpha = x[t];
+    else if (row > s && row < hi) sig2 += x[t] * x[t];
+  }
+  alpha = wave_sum(alpha);  // one non-zero term
+  sig2 = wave_sum(sig2);
+  if (sig2 == 0.0) {
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      const int row = r0 + lane + kWave * t;
+      if (row >= s && row < hi) vdst[row - s] = (row == s) ? 1.0 : 0.0;
+    }
+    return 0.0;
+  }
+  const double nrm = sqrt(alpha * alpha + sig2);
+  const double beta = (alpha >= 0.0) ? -nrm : nrm;
+  const double den = alpha - beta;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    const int row = r0 + lane + kWave * t;
+    if (row == s) {
+      x[t] = beta;
+      vdst[0] = 1.0;
+    } else if (row > s && row < hi) {
+      const double vi = x[t] / den;
+      x[t] = vi;
+      vdst[row - s] = vi;
+    }
+  }
+  return (beta - alpha) / beta;
+}
+
+// x_g <- (I - th v v^T) x_g for G columns held by one wave (v in vr, same row layout).
+template <int TT, int G>
+__device__ __forceinline__ void apply_refl(double (&x)[G][TT], const double (&vr)[TT], double th) {
+  double f[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    f[g] = 0.0;
+#pragma unroll
+    for (int t = 0; t < TT; ++t) f[g] += vr[t] * x[g][t];
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) f[g] = wave_sum(f[g]);
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int t = 0; t < TT; ++t) x[g][t] -= th * (vr[t] * f[g]);
+}
+
+template <int TT>
+__device__ __forceinline__ void apply_refl1(double (&x)[TT], const double (&vr)[TT], double th) {
+  double f = 0.0;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) f += vr[t] * x[t];
+  f = wave_sum(f);
+#pragma unroll
+  for (int t = 0; t < TT; ++t) x[t] -= th * (vr[t] * f);
+}
+
+// As apply_refl, with v read from LDS (row lane + 64 t at v[lane + 64 t], rows >= nv zero)
+// twice instead of being held in registers: for tall blocks.
+template <int TT, int G>
+__device__ __forceinline__ void apply_refl_lds(double (&x)[G][TT], const double *v, int nv, double th) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double f[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) f[g] = 0.0;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    const int rr = lane + kWave * t;
+    const double vv = (rr < nv) ? v[rr] : 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) f[g] += vv * x[g][t];
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) f[g] = wave_sum(f[g]);
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    const int rr = lane + kWave * t;
+    const double vv = (rr < nv) ? v[rr] : 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) x[g][t] -= th * (vv * f[g]);
+  }
+}
+
+// ---------------------------------------------------------------- unpivoted QR of the block
+// Reflector i of the current panel: Vp[i * ldv + (row - p)] for rows p..m-1 (zero above its
+// pivot row, 1 on it).  taus: [max_cols] in LDS.
+template <int T, int G, int NPC>
+__global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restrict__ M, double *__restrict__ Q,
+                                            double *__restrict__ tau0, int nb, const int32_t *__restrict__ order) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  {
+    const int j = order ? order[blockIdx.x] : blockIdx.x;
+    const Blk B = blk(L, j);
+    const int m = B.m, n = B.n, nr = B.nr;
+    double *__restrict__ A = Q + B.base;
+    const double *__restrict__ Mj = M + B.base;
+    double *taus = lds;
+    double *Vp = lds + L.max_cols;
+    const int ldv = m;
+    for (int64_t e = tid; e < (int64_t)m * n; e += NT) A[e] = Mj[e];
+    __syncthreads();
+    for (int p = 0; p < nr; p += nb) {
+      const int b = min(nb, nr - p);
+      // the panel's columns in registers: column p + w + NW u
+      double pc[NPC][T];
+#pragma unroll
+      for (int u = 0; u < NPC; ++u) {
+        const int k = p + w + NW * u;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const int row = p + lane + kWave * t;
+          pc[u][t] = (k < p + b && row < m) ? A[(int64_t)k * m + row] : 0.0;
+        }
+      }
+      for (int i = 0; i < b; ++i) {
+        const int s = p + i;
+        if (w == i % NW) {
+          double *vrow = Vp + (int64_t)i * ldv;
+          for (int rr = lane; rr < i; rr += kWave) vrow[rr] = 0.0;
+          double th;
+          if (NPC == 1 || i < NW) th = reflect<T>(pc[0], p, s, m, vrow + i);
+          else th = reflect<T>(pc[NPC - 1], p, s, m, vrow + i);
+          if (lane == 0) taus[s] = th;
+        }
+        __syncthreads();
+        const double th = taus[s];
+        if constexpr (T >= 24) {
+          if (p + w > s && p + w < p + b)
+            apply_refl_lds<T, 1>(reinterpret_cast<double(&)[1][T]>(pc[0]), Vp + (int64_t)i * ldv, m - p, th);
+        } else {
+          double vr[T];
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const int rr = lane + kWave * t;
+            vr[t] = (p + rr < m) ? Vp[(int64_t)i * ldv + rr] : 0.0;
+          }
+          if (p + w > s && p + w < p + b) apply_refl1<T>(pc[0], vr, th);
+          if (NPC > 1 && p + w + NW > s && p + w + NW < p + b) apply_refl1<T>(pc[NPC - 1], vr, th);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < NPC; ++u) {
+        const int k = p + w + NW * u;
+        if (k < p + b) {
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const int row = p + lane + kWave * t;
+            if (row < m) A[(int64_t)k * m + row] = pc[u][t];
+          }
+        }
+      }
+      // trailing columns: loaded once, the panel's reflectors in order, stored once
+      for (int c0 = p + b + w * G; c0 < n; c0 += NW * G) {
+        double x[G][T];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int k = c0 + g;
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const int row = p + lane + kWave * t;
+            x[g][t] = (k < n && row < m) ? A[(int64_t)k * m + row] : 0.0;
+          }
+        }
+        for (int i = 0; i < b; ++i) {
+          if constexpr (T >= 24) {
+            apply_refl_lds<T, G>(x, Vp + (int64_t)i * ldv, m - p, taus[p + i]);
+          } else {
+            double vr[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+              const int rr = lane + kWave * t;
+              vr[t] = (p + rr < m) ? Vp[(int64_t)i * ldv + rr] : 0.0;
+            }
+            apply_refl<T, G>(x, vr, taus[p + i]);
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int k = c0 + g;
+          if (k < n) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+              const int row = p + lane + kWave * t;
+              if (row < m) A[(int64_t)k * m + row] = x[g][t];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int k = tid; k < nr; k += NT) tau0[B.f0 + k] = taus[k];
+  }
+}
+
+// ---------------------------------------------------------------- pivoted QR of R0
+// Columns of R0 (rows 0..nr-1) live in slots: slot u < NREG is register slot u % S of wave
+// u / S, NREG <= u < NREG + nl is an LDS column, u >= NREG + nl is column u - NREG - nl of
+// the block's global slot W1 (ld nr).  Column c starts in slot c.  When the pivot comes
+// from a register or LDS slot, an active column of the global tier moves into the freed
+// slot, so the global tier drains as the factorisation proceeds.
+// LDS: sn, scol [nslot] (norm, -1 once retired or empty; column id, -1 empty), t1, ds, perm
+// [nmax], glist, gpos (global slots still active, and where each sits in glist), vbuf, pcol
+// [64 TR], red/ired, regact [NW] (active register slots of each wave), then the LDS tier.
+__host__ __device__ constexpr size_t qrcp_small_bytes(int nmax, int nreg, int tr) {
+  return (size_t)(2 * nmax + (nmax + nreg) + 2 * kWave * tr + 32) * sizeof(double) +
+         (size_t)(2 * (nmax + nreg) + 2 * nmax + 64 + NW + 2) * sizeof(int) + 8;
+}
+
+template <int TR, int S>
+__global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__restrict__ Q, double tau,
+                                              int32_t *__restrict__ rank_out, int32_t *__restrict__ kept,
+                                              double *__restrict__ Rout, double *__restrict__ ratios,
+                                              double *__restrict__ tau1, double *__restrict__ dsgn,
+                                              double *__restrict__ W1, int64_t tier_doubles,
+                                              const int32_t *__restrict__ order) {
+  extern __shared__ double lds[];
+  constexpr int NREG = NW * S;
+  constexpr int CH = S < 8 ? S : 8;
+  constexpr int TB = TR <= 2 ? 4 : 2;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int nmax = L.max_cols, nsl = nmax + NREG;
+  double *sn = lds;                  // [nsl]
+  double *t1 = sn + nsl;             // [nmax]
+  double *ds = t1 + nmax;            // [nmax]
+  double *vbuf = ds + nmax;          // [64 TR]
+  double *pcol = vbuf + kWave * TR;  // [64 TR]
+  double *red = pcol + kWave * TR;   // [32]
+  int *scol = (int *)(red + 32);     // [nsl]
+  int *gpos = scol + nsl;            // [nsl]
+  int *perm = gpos + nsl;            // [nmax]
+  int *glist = perm + nmax;          // [nmax]
+  int *ired = glist + nmax;          // [64]
+  unsigned *regact = (unsigned *)(ired + 64);  // [NW]
+  int *gcnt = (int *)(regact + NW);             // [2]
+  double *tier = (double *)((((uintptr_t)(gcnt + 2)) + 7) & ~(uintptr_t)7);
+
+  const int j = order ? order[blockIdx.x] : blockIdx.x;
+  const Blk B = blk(L, j);
+  const int m = B.m, n = B.n, nr = B.nr;
+  const double *__restrict__ A = Q + B.base;
+  double *__restrict__ R = Rout + B.rsq;
+  double *__restrict__ Wg = W1 + B.rsq;
+  const int nl = (nr > 0) ? (int)min((int64_t)max(n - NREG, 0), tier_doubles / nr) : 0;
+  const int gbase = NREG + nl;        // first global slot
+  const int nslot = max(n, NREG);     // slots in use
+
+  // ---- R0 (upper triangle of the factored block) into the tiers, initial norms
+  double xs[S][TR];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const int c = w * S + q;
+    double ss = 0.0;
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      const int row = lane + kWave * t;
+      const bool ok = c < n && row < nr && row <= c;
+      xs[q][t] = ok ? A[(int64_t)c * m + row] : 0.0;
+      ss += xs[q][t] * xs[q][t];
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) {
+      sn[c] = (c < n) ? sqrt(ss) : -1.0;
+      scol[c] = (c < n) ? c : -1;
+    }
+  }
+  for (int c = NREG + w; c < n; c += NW) {
+    double ss = 0.0;
+    double *dst = (c < gbase) ? tier + (int64_t)(c - NREG) * nr : Wg + (int64_t)(c - gbase) * nr;
+    for (int row = lane; row < nr; row += kWave) {
+      const double a = (row <= c) ? A[(int64_t)c * m + row] : 0.0;
+      dst[row] = a;
+      ss += a * a;
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) {
+      sn[c] = sqrt(ss);
+      scol[c] = c;
+    }
+  }
+  for (int u = gbase + tid; u < n; u += NT) {
+    glist[u - gbase] = u;
+    gpos[u] = u - gbase;
+  }
+  if (tid < NW) {
+    unsigned bits = 0;
+    for (int q = 0; q < S; ++q)
+      if (tid * S + q < n) bits |= 1u << q;
+    regact[tid] = bits;
+  }
+  if (tid == 0) gcnt[0] = max(n - gbase, 0);
+  if (ratios)
+    for (int c = tid; c < n; c += NT) ratios[B.f0 + c] = 0.0;
+  __syncthreads();
+
+  int r = nr;
+  double ref = 0.0;
+  for (int s = 0; s < nr; ++s) {
+    // ---- pivot: largest trailing norm, ties to the smallest column
+    double best = -0.5;
+    int bid = 0x7fffffff, bu = -1;
+    for (int u = tid; u < nslot; u += NT) {
+      const double cv = sn[u];
+      const int c = scol[u];
+      if (cv > best || (cv == best && c < bid)) {
+        best = cv;
+        bid = c;
+        bu = u;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, kWave);
+      const int oid = __shfl_xor(bid, off, kWave);
+      const int ou = __shfl_xor(bu, off, kWave);
+      if (ob > best || (ob == best && oid < bid)) {
+        best = ob;
+        bid = oid;
+        bu = ou;
+      }
+    }
+    if (lane == 0) {
+      red[w] = best;
+      ired[w] = bid;
+      ired[32 + w] = bu;
+    }
+    __syncthreads();
+    best = red[0];
+    bid = ired[0];
+    bu = ired[32];
+    for (int ww = 1; ww < NW; ++ww) {
+      const double ob = red[ww];
+      const int oid = ired[ww];
+      if (ob > best || (ob == best && oid < bid)) {
+        best = ob;
+        bid = oid;
+        bu = ired[32 + ww];
+      }
+    }
+    if (s == 0) ref = best;
+    if (ref == 0.0) {  // zero block: nothing is kept
+      r = 0;
+      break;
+    }
+    if (tid == 0 && ratios) ratios[B.f0 + s] = best / ref;
+    if (best <= tau * ref) {
+      r = s;
+      break;
+    }
+    const int P = bid, U = bu;
+
+    // ---- the pivot column to LDS by the wave that holds it; a global column refills the slot
+    const int owner = (U < NREG) ? U / S : 0;
+    if (w == owner) {
+      const int gc = gcnt[0];
+      const int g = (U < gbase && gc > 0) ? glist[gc - 1] : -1;
+      const double *gsrc = (g >= 0) ? Wg + (int64_t)(g - gbase) * nr : nullptr;
+      if (U < NREG) {
+        const int qp = U - owner * S;
+#pragma unroll
+        for (int q = 0; q < S; ++q)
+          if (q == qp) {
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+              const int row = lane + kWave * t;
+              if (row < nr) pcol[row] = xs[q][t];
+              if (gsrc) xs[q][t] = (row < nr) ? gsrc[row] : 0.0;
+            }
+          }
+      } else {
+        double *src = (U < gbase) ? tier + (int64_t)(U - NREG) * nr : Wg + (int64_t)(U - gbase) * nr;
+        for (int row = lane; row < nr; row += kWave) {
+          pcol[row] = src[row];
+          if (gsrc) src[row] = gsrc[row];
+        }
+      }
+      if (lane == 0) {
+        perm[s] = P;
+        if (g >= 0) {  // slot U takes column scol[g]; g (the last of glist) leaves the global tier
+          scol[U] = scol[g];
+          sn[U] = sn[g];
+          scol[g] = -1;
+          sn[g] = -1.0;
+          gcnt[0] = gc - 1;
+        } else {
+          sn[U] = -1.0;
+          scol[U] = -1;
+          if (U < NREG) regact[owner] &= ~(1u << (U - owner * S));
+          if (U >= gbase) {  // swap-remove U from glist
+            const int k = gpos[U], last = glist[gc - 1];
+            glist[k] = last;
+            gpos[last] = k;
+            gcnt[0] = gc - 1;
+          }
+        }
+      }
+    }
+    __syncthreads();  // pcol complete; everyone has read red/ired
+
+    // ---- reflector (wave 0); column s of the R slot: R_hat entries with normalised signs
+    // on and above the diagonal, the reflector below it
+    if (w == 0) {
+      double x[TR];
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int row = lane + kWave * t;
+        x[t] = (row < nr) ? pcol[row] : 0.0;
+      }
+      const double th = reflect<TR>(x, 0, s, nr, vbuf);
+      double dg = 0.0;
+#pragma unroll
+      for (int t = 0; t < TR; ++t)
+        if (lane + kWave * t == s) dg = x[t];
+      dg = wave_sum(dg);
+      const double sg = (dg < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int row = lane + kWave * t;
+        if (row < nr) R[(int64_t)s * n + row] = (row < s) ? ds[row] * x[t] : (row == s) ? sg * x[t] : x[t];
+      }
+      if (lane == 0) {
+        t1[s] = th;
+        ds[s] = sg;
+      }
+    }
+    __syncthreads();
+
+    // ---- every active column takes the reflector; norms recomputed from the new entries
+    const double th = t1[s];
+    double vr[TR];
+#pragma unroll
+    for (int t = 0; t < TR; ++t) {
+      const int row = lane + kWave * t;
+      vr[t] = (row >= s && row < nr) ? vbuf[row - s] : 0.0;
+    }
+    // register tier, CH slots at a time (their reductions overlap)
+    const unsigned act = regact[w];
+#pragma unroll
+    for (int q0 = 0; q0 < S; q0 += CH) {
+      double f[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        f[u] = 0.0;
+        if (q0 + u < S) {
+#pragma unroll
+          for (int t = 0; t < TR; ++t) f[u] += vr[t] * xs[q0 + u][t];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) f[u] = wave_sum(f[u]);
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        if (q0 + u < S) {
+          const double sc = ((act >> (q0 + u)) & 1u) ? th : 0.0;
+          double ss = 0.0;
+#pragma unroll
+          for (int t = 0; t < TR; ++t) {
+            xs[q0 + u][t] -= sc * (vr[t] * f[u]);
+            const int row = lane + kWave * t;
+            const double xv = (row > s && row < nr) ? xs[q0 + u][t] : 0.0;
+            ss += xv * xv;
+          }
+          f[u] = ss;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) f[u] = wave_sum(f[u]);
+      if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+          if (q0 + u < S && ((act >> (q0 + u)) & 1u)) sn[w * S + q0 + u] = sqrt(f[u]);
+      }
+    }
+    // LDS tier, then the global tier (by glist), TB columns per wave at a time
+    const int gc = gcnt[0];
+    const int nother = nl + gc;
+    for (int k0 = TB * w; k0 < nother; k0 += TB * NW) {
+      double x[TB][TR], sc[TB];
+      double *col[TB];
+      int us[TB];
+#pragma unroll
+      for (int g = 0; g < TB; ++g) {
+        const int k = k0 + g;
+        int u = -1;
+        if (k < nl) u = NREG + k;
+        else if (k < nother) u = glist[k - nl];
+        const bool live = u >= 0 && sn[u] >= 0.0;
+        us[g] = live ? u : -1;
+        sc[g] = live ? th : 0.0;
+        col[g] = !live ? nullptr : (u < gbase) ? tier + (int64_t)(u - NREG) * nr : Wg + (int64_t)(u - gbase) * nr;
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+          const int row = lane + kWave * t;
+          x[g][t] = (live && row >= s && row < nr) ? col[g][row] : 0.0;
+        }
+      }
+      double f[TB];
+#pragma unroll
+      for (int g = 0; g < TB; ++g) {
+        f[g] = 0.0;
+#pragma unroll
+        for (int t = 0; t < TR; ++t) f[g] += vr[t] * x[g][t];
+      }
+#pragma unroll
+      for (int g = 0; g < TB; ++g) f[g] = wave_sum(f[g]);
+#pragma unroll
+      for (int g = 0; g < TB; ++g) {
+        double ss = 0.0;
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+          x[g][t] -= sc[g] * (vr[t] * f[g]);
+          const int row = lane + kWave * t;
+          const double xv = (row > s && row < nr) ? x[g][t] : 0.0;
+          ss += xv * xv;
+        }
+        f[g] = ss;
+      }
+#pragma unroll
+      for (int g = 0; g < TB; ++g) f[g] = wave_sum(f[g]);
+#pragma unroll
+      for (int g = 0; g < TB; ++g) {
+        if (col[g]) {
+#pragma unroll
+          for (int t = 0; t < TR; ++t) {
+            const int row = lane + kWave * t;
+            if (row >= s && row < nr) col[g][row] = x[g][t];
+          }
+          if (lane == 0) sn[us[g]] = sqrt(f[g]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- outputs: the rest of the R slot cleared, kept ids, scalars
+  for (int64_t e = tid; e < (int64_t)n * n; e += NT) {
+    const int q = (int)(e / n), row = (int)(e % n);
+    if (q >= r || row >= nr) R[e] = 0.0;
+  }
+  if (tid == 0) rank_out[j] = r;
+  for (int q = tid; q < n; q += NT) {
+    kept[B.f0 + q] = (q < r) ? perm[q] : -1;
+    if (q < r) {
+      tau1[B.f0 + q] = t1[q];
+      dsgn[B.f0 + q] = ds[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Q1 = H'_0..H'_{r-1} [I_r; 0]
+// Backward over panels of nb reflectors (read from below the diagonal of the R slot, which
+// is cleared as it is consumed); the result Z (nr x r, ld nr) in the block's slot W2.
+template <int TR, int G>
+__global__ __launch_bounds__(NT) void rf_formq1(rfm_layout L, const int32_t *__restrict__ rank,
+                                                double *__restrict__ Rout, const double *__restrict__ tau1,
+                                                double *__restrict__ W2, int nb,
+                                                const int32_t *__restrict__ order) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  {
+    const int j = order ? order[blockIdx.x] : blockIdx.x;
+    const Blk B = blk(L, j);
+    const int n = B.n, nr = B.nr, r = rank[j];
+    if (r == 0) return;
+    double *__restrict__ R = Rout + B.rsq;
+    double *__restrict__ Z = W2 + B.rsq;
+    double *tl = lds;       // [nb]
+    double *Vp = lds + 16;  // [nb][nr]
+    for (int p = ((r - 1) / nb) * nb; p >= 0; p -= nb) {
+      const int b = min(nb, r - p);
+      for (int e = tid; e < b * (nr - p); e += NT) {
+        const int i = e / (nr - p), rr = e % (nr - p);
+        const int q = p + i, row = p + rr;
+        Vp[i * nr + rr] = (rr < i) ? 0.0 : (rr == i) ? 1.0 : R[(int64_t)q * n + row];
+      }
+      for (int i = tid; i < b; i += NT) tl[i] = tau1[B.f0 + p + i];
+      __syncthreads();
+      for (int e = tid; e < b * (nr - p); e += NT) {
+        const int i = e / (nr - p), rr = e % (nr - p);
+        if (rr > i) R[(int64_t)(p + i) * n + p + rr] = 0.0;
+      }
+      for (int c0 = p + w * G; c0 < r; c0 += NW * G) {
+        double x[G][TR];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int k = c0 + g;
+#pragma unroll
+          for (int t = 0; t < TR; ++t) {
+            const int row = p + lane + kWave * t;
+            double v = 0.0;
+            if (k < r && row < nr) v = (k < p + b) ? (row == k ? 1.0 : 0.0) : Z[(int64_t)k * nr + row];
+            x[g][t] = v;
+          }
+        }
+        for (int i = b - 1; i >= 0; --i) {
+          double vr[TR];
+#pragma unroll
+          for (int t = 0; t < TR; ++t) {
+            const int rr = lane + kWave * t;
+            vr[t] = (p + rr < nr) ? Vp[i * nr + rr] : 0.0;
+          }
+          apply_refl<TR, G>(x, vr, tl[i]);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int k = c0 + g;
+          if (k < r) {
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+              const int row = p + lane + kWave * t;
+              if (row < nr) Z[(int64_t)k * nr + row] = x[g][t];
+            }
+            if (k < p + b)
+              for (int row = lane; row < p; row += kWave) Z[(int64_t)k * nr + row] = 0.0;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Q0 = H_0..H_{nr-1} [I; 0]
+// In place in the Q slot, backward over panels: the panel's reflectors go to LDS first, so
+// its columns can be overwritten; columns left of the panel still hold their reflectors.
+template <int T, int G>
+__global__ __launch_bounds__(NT) void rf_formq0(rfm_layout L, const int32_t *__restrict__ rank,
+                                                double *__restrict__ Q, const double *__restrict__ tau0, int nb,
+                                                const int32_t *__restrict__ order) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  {
+    const int j = order ? order[blockIdx.x] : blockIdx.x;
+    const Blk B = blk(L, j);
+    const int m = B.m, nr = B.nr;
+    if (rank[j] == 0) return;
+    double *__restrict__ A = Q + B.base;
+    double *tl = lds;       // [nb]
+    double *Vp = lds + 16;  // [nb][m]
+    for (int p = ((nr - 1) / nb) * nb; p >= 0; p -= nb) {
+      const int b = min(nb, nr - p);
+      for (int e = tid; e < b * (m - p); e += NT) {
+        const int i = e / (m - p), rr = e % (m - p);
+        const int k = p + i, row = p + rr;
+        Vp[(int64_t)i * m + rr] = (rr < i) ? 0.0 : (rr == i) ? 1.0 : A[(int64_t)k * m + row];
+      }
+      for (int i = tid; i < b; i += NT) tl[i] = tau0[B.f0 + p + i];
+      __syncthreads();
+      for (int c0 = p + w * G; c0 < nr; c0 += NW * G) {
+        double x[G][T];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int k = c0 + g;
+#pragma unroll
+          for (int t = 0; t < T; ++t) {
+            const int row = p + lane + kWave * t;
+            double v = 0.0;
+            if (k < nr && row < m) v = (k < p + b) ? (row == k ? 1.0 : 0.0) : A[(int64_t)k * m + row];
+            x[g][t] = v;
+          }
+        }
+        for (int i = b - 1; i >= 0; --i) {
+          if constexpr (T >= 24) {
+            apply_refl_lds<T, G>(x, Vp + (int64_t)i * m, m - p, tl[i]);
+          } else {
+            double vr[T];
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+              const int rr = lane + kWave * t;
+              vr[t] = (p + rr < m) ? Vp[(int64_t)i * m + rr] : 0.0;
+            }
+            apply_refl<T, G>(x, vr, tl[i]);
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int k = c0 + g;
+          if (k < nr) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+              const int row = p + lane + kWave * t;
+              if (row < m) A[(int64_t)k * m + row] = x[g][t];
+            }
+            if (k < p + b)
+              for (int row = lane; row < p; row += kWave) A[(int64_t)k * m + row] = 0.0;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Q_hat = Q0 Q1 D in place
+// Row tiles of RT rows of Q0 (nr columns) staged in LDS as tile[k * RT + row]; lane <-> row,
+// eight output columns per pass, Q1 entries broadcast from the W2 slot.
+template <int RT>
+__global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__restrict__ rank,
+                                              double *__restrict__ Q, const double *__restrict__ W2,
+                                              const double *__restrict__ dsgn, const int32_t *__restrict__ order) {
+  extern __shared__ double lds[];
+  constexpr int NS = kWave / RT;  // output groups per wave
+  constexpr int GQ = 8;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int row = lane % RT, sub = lane / RT;
+  {
+    const int j = order ? order[blockIdx.x] : blockIdx.x;
+    const Blk B = blk(L, j);
+    const int m = B.m, nr = B.nr, r = rank[j];
+    if (r == 0) return;
+    double *__restrict__ A = Q + B.base;
+    const double *__restrict__ Z = W2 + B.rsq;
+    for (int i0 = 0; i0 < m; i0 += RT) {
+      const int rows = min(RT, m - i0);
+      for (int e = tid; e < nr * RT; e += NT) {
+        const int k = e / RT, rr = e % RT;
+        lds[e] = (rr < rows) ? A[(int64_t)k * m + i0 + rr] : 0.0;
+      }
+      __syncthreads();
+      for (int q0 = (w * NS + sub) * GQ; q0 < r; q0 += NW * NS * GQ) {
+        double acc[GQ];
+        const double *zc[GQ];
+#pragma unroll
+        for (int g = 0; g < GQ; ++g) {
+          acc[g] = 0.0;
+          zc[g] = Z + (int64_t)min(q0 + g, r - 1) * nr;
+        }
+        for (int k = 0; k < nr; ++k) {
+          const double a = lds[k * RT + row];
+#pragma unroll
+          for (int g = 0; g < GQ; ++g) acc[g] += a * zc[g][k];
+        }
+        if (row < rows) {
+#pragma unroll
+          for (int g = 0; g < GQ; ++g) {
+            const int q = q0 + g;
+            if (q < r) A[(int64_t)q * m + i0 + row] = dsgn[B.f0 + q] * acc[g];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Ws {
+  double *tau0, *tau1, *dsgn, *W1, *W2;
+};
+
+size_t carve(const rfm_layout *L, char *base, Ws *W) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += al256(bytes);
+    return p;
+  };
+  const size_t nc = (size_t)(L->ncols > 0 ? L->ncols : 1), nq = (size_t)(L->nrsq > 0 ? L->nrsq : 1);
+  Ws w;
+  w.tau0 = (double *)take(nc * sizeof(double));
+  w.tau1 = (double *)take(nc * sizeof(double));
+  w.dsgn = (double *)take(nc * sizeof(double));
+  w.W1 = (double *)take(nq * sizeof(double));
+  w.W2 = (double *)take(nq * sizeof(double));
+  if (W) *W = w;
+  return off;
+}
+
+constexpr int g_of(int T) { return T <= 4 ? 8 : T <= 12 ? 4 : T <= 16 ? 2 : 1; }
+constexpr int npc_of(int T) { return T <= 16 ? 2 : 1; }
+
+template <class K>
+rfm_status prep(K kern, size_t lds) {
+  RFM_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  return RFM_OK;
+}
+
+template <int T>
+rfm_status launch_tall(const RfirstArgs &a, const Ws &W, int nb, bool first) {
+  const rfm_layout *L = a.L;
+  constexpr int GG = g_of(T);
+  const dim3 grid((unsigned)L->J);
+  if (first) {
+    const size_t lds = ((size_t)L->max_cols + (size_t)nb * L->max_rows) * sizeof(double);
+    auto kern = rf_qr<T, GG, npc_of(T)>;
+    rfm_status s = prep(kern, lds);
+    if (s != RFM_OK) return s;
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, a.st, *L, a.M, a.Q, W.tau0, nb, a.order);
+  } else {
+    const size_t lds = (16 + (size_t)nb * L->max_rows) * sizeof(double);
+    auto kern = rf_formq0<T, GG>;
+    rfm_status s = prep(kern, lds);
+    if (s != RFM_OK) return s;
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, a.st, *L, a.rank, a.Q, W.tau0, nb, a.order);
+  }
+  RFM_LAUNCH_CHECK();
+  return RFM_OK;
+}
+
+rfm_status dispatch_tall(const RfirstArgs &a, const Ws &W, int nb, bool first) {
+  const int mr = a.L->max_rows;
+  if (mr <= 64) return launch_tall<1>(a, W, nb, first);
+  if (mr <= 128) return launch_tall<2>(a, W, nb, first);
+  if (mr <= 256) return launch_tall<4>(a, W, nb, first);
+  if (mr <= 512) return launch_tall<8>(a, W, nb, first);
+  if (mr <= 768) return launch_tall<12>(a, W, nb, first);
+  if (mr <= 1024) return launch_tall<16>(a, W, nb, first);
+  if (mr <= 1536) return launch_tall<24>(a, W, nb, first);
+  if (mr <= 2048) return launch_tall<32>(a, W, nb, first);
+  return launch_tall<48>(a, W, nb, first);
+}
+
+template <int TR, int S, int GQ1>
+rfm_status launch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
+  const rfm_layout *L = a.L;
+  const dim3 grid((unsigned)L->J);
+  const int nmax = L->max_cols;
+  const size_t small = qrcp_small_bytes(nmax, NW * S, TR);
+  const int64_t want = (int64_t)std::max(0, nmax - NW * S) * nr_max;
+  int64_t tier = (int64_t)((kLdsCap - small) / sizeof(double));
+  if (tier > want) tier = want;
+  if (tier < 0) tier = 0;
+  const size_t lds = small + (size_t)tier * sizeof(double);
+  {
+    auto kern = rf_qrcp<TR, S>;
+    rfm_status s = prep(kern, lds);
+    if (s != RFM_OK) return s;
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds, a.st, *L, (const double *)a.Q, a.tau, a.rank, a.kept, a.R,
+                       a.ratios, W.tau1, W.dsgn, W.W1, tier, a.order);
+    RFM_LAUNCH_CHECK();
+  }
+  {
+    const int nb = 16;
+    const size_t lds1 = (16 + (size_t)nb * nr_max) * sizeof(double);
+    auto kern = rf_formq1<TR, GQ1>;
+    rfm_status s = prep(kern, lds1);
+    if (s != RFM_OK) return s;
+    hipLaunchKernelGGL(kern, grid, dim3(NT), lds1, a.st, *L, a.rank, a.R, W.tau1, W.W2, nb, a.order);
+    RFM_LAUNCH_CHECK();
+  }
+  return RFM_OK;
+}
+
+rfm_status dispatch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
+  if (nr_max <= 64) return launch_small<1, 32, 8>(a, W, nr_max);
+  if (nr_max <= 128) return launch_small<2, 24, 8>(a, W, nr_max);
+  if (nr_max <= 256) return launch_small<4, 14, 4>(a, W, nr_max);
+  if (nr_max <= 320) return launch_small<5, 11, 4>(a, W, nr_max);
+  return launch_small<8, 6, 2>(a, W, nr_max);
+}
+
+}  // namespace
+
+bool rfirst_supported(const rfm_layout *L) { return L && L->max_cols <= 512 && L->max_rows <= 3072; }
+
+size_t rfirst_ws_bytes(const rfm_layout *L) { return carve(L, nullptr, nullptr); }
+
+rfm_status rrqr_rfirst(const RfirstArgs &a) {
+  const rfm_layout *L = a.L;
+  if (!rfirst_supported(L)) return fail(RFM_EUNSUPPORTED, "rfm_rrqr_filter: the R-first form needs max_cols <= 512");
+  if (!a.ws || a.ws_bytes < rfirst_ws_bytes(L))
+    return fail(RFM_EINVAL, "rfm_rrqr_filter: workspace too small (rfm_rrqr_ws_bytes)");
+  if (L->J < 1) return RFM_OK;
+  Ws W;
+  carve(L, (char *)a.ws, &W);
+  const int nr_max = std::max(1, std::min(L->max_rows, L->max_cols));
+  const int mr = std::max(1, L->max_rows);
+  // panel width of the tall passes: nb reflectors of max_rows entries in LDS, at most the
+  // panel columns the waves hold in registers
+  int nb = (int)((140 * 1024 - (size_t)L->max_cols * sizeof(double)) / ((size_t)mr * sizeof(double)));
+  nb = std::max(1, std::min(mr > 1024 ? NW : 2 * NW, nb));
+  rfm_status s = dispatch_tall(a, W, nb, true);
+  if (s != RFM_OK) return s;
+  s = dispatch_small(a, W, nr_max);
+  if (s != RFM_OK) return s;
+  s = dispatch_tall(a, W, nb, false);
+  if (s != RFM_OK) return s;
+  const dim3 grid((unsigned)L->J);
+  const int RT = ((size_t)nr_max * 64 * sizeof(double) <= 140 * 1024) ? 64 : 32;
+  const size_t lds = (size_t)nr_max * RT * sizeof(double);
+  if (RT == 64) {
+    s = prep(rf_gemm<64>, lds);
+    if (s != RFM_OK) return s;
+    hipLaunchKernelGGL(rf_gemm<64>, grid, dim3(NT), lds, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
+  } else {
+    s = prep(rf_gemm<32>, lds);
+    if (s != RFM_OK) return s;
+    hipLaunchKernelGGL(rf_gemm<32>, grid, dim3(NT), lds, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
+  }
+  RFM_LAUNCH_CHECK();
+  return RFM_OK;
+}
+
+}  // namespace rfm

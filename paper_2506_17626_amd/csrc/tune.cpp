@@ -39,12 +39,14 @@ extern "C" rfm_status rfm_autotune(const rfm_layout *L, const double *M, double 
     return fail(RFM_EHIP, "rfm_autotune: hipEventCreate");
 
   std::vector<rfm_tuning> cands;
+  if (L->max_cols <= 512)  // R-first form: one block per workgroup in the given order
+    cands.push_back(rfm_tuning{0, 0, 1, 0, RFM_RRQR_RFIRST});
   const int threads[3] = {256, 512, 1024};
   for (int t : threads) {
     if (t == 1024 && L->max_rows > 1024) continue;
-    cands.push_back(rfm_tuning{t, 0, 1, 0});
-    cands.push_back(rfm_tuning{t, 1, 1, 0});
-    cands.push_back(rfm_tuning{t, 1, 2, 0});
+    cands.push_back(rfm_tuning{t, 0, 1, 0, RFM_RRQR_DIRECT});
+    cands.push_back(rfm_tuning{t, 1, 1, 0, RFM_RRQR_DIRECT});
+    cands.push_back(rfm_tuning{t, 1, 2, 0, RFM_RRQR_DIRECT});
   }
   int32_t n = 0;
   double best_ms = 1e300;
@@ -68,6 +70,10 @@ extern "C" rfm_status rfm_autotune(const rfm_layout *L, const double *M, double 
       win = c;
     }
   }
+
+  // the outputs are those of the winning filter shape
+  s = rfm_rrqr_filter_tuned(L, M, tau, rank, kept, R, Q, ratios, order, &win, ws, ws_bytes, stream);
+  if (s != RFM_OK) return s;
 
   // adjoint tile of LSQR: sampled stage times of a short solve per candidate
   rfm_operator A{};

@@ -21,6 +21,7 @@ _lib = C.CDLL(_LIB_PATH)
 
 RFM_OK, RFM_EINVAL, RFM_EHIP, RFM_ENOTCONV, RFM_EUNSUPPORTED = 0, 1, 3, 4, 5
 FORM_Q, FORM_R = 0, 1
+RRQR_AUTO, RRQR_DIRECT, RRQR_RFIRST = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
 
 _p = C.c_void_p
@@ -49,7 +50,7 @@ class Operator(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("rrqr_threads", C.c_int32), ("rrqr_persistent", C.c_int32), ("rrqr_wgs_per_cu", C.c_int32),
-                ("adj_tile", C.c_int32)]
+                ("adj_tile", C.c_int32), ("rrqr_algo", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

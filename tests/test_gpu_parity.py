@@ -90,11 +90,11 @@ def test_assembly_full_size_sampled_blocks(rfm):
         assert np.all(np.abs(got - ref) <= 32 * U * scale)
 
 
-def _gpu_rrqr_on(rfm, inst, blocks, tau):
+def _gpu_rrqr_on(rfm, inst, blocks, tau, algo=0):
     plan = rfm.plan_instance(inst)
     K = np.diff(inst.feat_off)
     M = _dev(H.pack_blocks(plan.host, blocks, K))
-    out = rfm.rfm_rrqr_filter(plan, M, tau)
+    out = rfm.rfm_rrqr_filter(plan, M, tau, tune=rfm.Tuning(rrqr_algo=algo))
     torch.cuda.synchronize()
     return plan, {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
 
@@ -128,23 +128,29 @@ def _compare_rrqr(plan, out, blocks, facts, K, tau):
     return mismatches
 
 
+ALGOS = {"rfirst": 2, "direct": 1}
+
+
+@pytest.mark.parametrize("algo", sorted(ALGOS))
 @pytest.mark.parametrize("name", TINY)
 @pytest.mark.parametrize("tau", [1e-12, 1e-8, 0.0])
-def test_rrqr_matches_oracle(rfm, name, tau):
+def test_rrqr_matches_oracle(rfm, name, tau, algo):
+    """Both factorisations of the filter (R-first and direct) against the oracle's QRCP."""
     inst = I.tiny(name)
-    print(f"[rrqr] {name} tau={tau}", flush=True)
+    print(f"[rrqr] {algo} {name} tau={tau}", flush=True)
     rows, blocks, _ = assembly.assemble(inst)
     facts = rrqr.filter_blocks(blocks, tau)
-    plan, out = _gpu_rrqr_on(rfm, inst, blocks, tau)
+    plan, out = _gpu_rrqr_on(rfm, inst, blocks, tau, ALGOS[algo])
     mm = _compare_rrqr(plan, out, blocks, facts, np.diff(inst.feat_off), tau)
     print(f"  accepted tie mismatches: {mm}", flush=True)
 
 
-def test_rrqr_full_size_sampled_blocks(rfm):
+@pytest.mark.parametrize("algo", sorted(ALGOS))
+def test_rrqr_full_size_sampled_blocks(rfm, algo):
     inst = I.workload("poisson2d")
-    print("[rrqr] poisson2d full size, sampled blocks", flush=True)
+    print(f"[rrqr] {algo} poisson2d full size, sampled blocks", flush=True)
     rows, blocks, _ = assembly.assemble(inst)
-    plan, out = _gpu_rrqr_on(rfm, inst, blocks, 1e-12)
+    plan, out = _gpu_rrqr_on(rfm, inst, blocks, 1e-12, ALGOS[algo])
     K = np.diff(inst.feat_off)
     picks = [0, 1, 17, 120, 255]
     facts = [rrqr.qrcp_filter(blocks[j], 1e-12) for j in picks]
@@ -157,7 +163,8 @@ def test_rrqr_full_size_sampled_blocks(rfm):
         assert np.max(np.abs(Rg - f.R)) <= 1e-12 * np.linalg.norm(blocks[j])
 
 
-def test_rrqr_edge_cases(rfm):
+@pytest.mark.parametrize("algo", sorted(ALGOS))
+def test_rrqr_edge_cases(rfm, algo):
     # a zero block, a duplicated column, a wide block, and a block with no rows
     rng = np.random.default_rng(3)
     inst = I.poisson1d(S=4, K=12, n=6, rho=0.3)
@@ -174,7 +181,7 @@ def test_rrqr_edge_cases(rfm):
     assert any(b.shape[0] < b.shape[1] for b in blocks[:4])   # wide blocks (m < n)
     assert blocks[4].shape[0] == 0
     facts = rrqr.filter_blocks(blocks, 1e-12)
-    plan, out = _gpu_rrqr_on(rfm, inst, blocks, 1e-12)
+    plan, out = _gpu_rrqr_on(rfm, inst, blocks, 1e-12, ALGOS[algo])
     assert out["rank"][0] == 0 and out["rank"][4] == 0
     _compare_rrqr(plan, out, blocks, facts, np.diff(inst.feat_off), 1e-12)
     kept1 = out["kept"][plan.host["feat_off"][1]:plan.host["feat_off"][1] + out["rank"][1]]
@@ -397,34 +404,61 @@ def test_precision_form_reaches_binary64_solution(rfm, dtype, name, tau):
     assert rel <= 1e-9 * kappa
 
 
+def test_precision_form_warm_start_guard(rfm):
+    """The refined solve applies the warm-start guard on its binary64 residual: a harmful start
+    is dropped and the solve is then the cold one, bit for bit; a good start is kept."""
+    inst = I.tiny("poisson2d")
+    rows, blocks, h, facts, plan, fact = _shared_fact(rfm, inst, 1e-8)
+    fact["Qlow"] = rfm.rfm_pack_q(plan, fact, rfm.F32)
+    kw = dict(atol=1e-10, btol=1e-10, maxit=50000, inner_dtype=rfm.F32, inner_tol=1e-6)
+    yc, ic = rfm.rfm_lsqr_solve(plan, fact, _dev(h), **kw)
+    bad = torch.full_like(yc, 1e6)
+    yb, ib = rfm.rfm_lsqr_solve(plan, fact, _dev(h), y0=bad, **kw)
+    assert ib.warm_rejected == 1 and ib.iters == ic.iters and torch.equal(yb, yc)
+    yg, ig = rfm.rfm_lsqr_solve(plan, fact, _dev(h), y0=yc.clone(), **kw)
+    assert ig.warm_rejected == 0 and ig.stop in (1, 2, 4) and ig.iters < ic.iters
+
+
 def test_batching_form_results_independent_of_order_and_launch_shape(rfm):
-    """Persistent launch with the cost order and every workgroup size give bitwise the same
-    factors as the default launch (each column is reduced by one wave in a fixed order)."""
+    """Within each factorisation the results are bitwise independent of the block order and
+    the launch shape: the R-first form in cost order, and the direct form with the persistent
+    launch and every workgroup size (each column is reduced by one wave in a fixed order)."""
     inst = I.tiny("helmholtz2d_uneven")
     rows, blocks, _ = assembly.assemble(inst)
     plan = rfm.plan_instance(inst)
     K = np.diff(inst.feat_off)
     M = _dev(H.pack_blocks(plan.host, blocks, K))
-    ref = rfm.rfm_rrqr_filter(plan, M, 1e-12)
     order = rfm.rfm_plan_order(plan)
+    ref = rfm.rfm_rrqr_filter(plan, M, 1e-12)
+    out = rfm.rfm_rrqr_filter(plan, M, 1e-12, order=order, tune=rfm.Tuning(rrqr_algo=rfm.RRQR_RFIRST))
+    torch.cuda.synchronize()
+    for k in ("rank", "kept", "R", "Q", "ratios"):
+        assert torch.equal(out[k], ref[k]), ("rfirst", k)
+    ref = rfm.rfm_rrqr_filter(plan, M, 1e-12, tune=rfm.Tuning(rrqr_algo=rfm.RRQR_DIRECT))
     for threads in (256, 512, 1024):
         for persistent, wgs in ((0, 1), (1, 1), (1, 2)):
-            tune = rfm.Tuning(rrqr_threads=threads, rrqr_persistent=persistent, rrqr_wgs_per_cu=wgs)
+            tune = rfm.Tuning(rrqr_threads=threads, rrqr_persistent=persistent, rrqr_wgs_per_cu=wgs,
+                              rrqr_algo=rfm.RRQR_DIRECT)
             out = rfm.rfm_rrqr_filter(plan, M, 1e-12, order=order, tune=tune)
             torch.cuda.synchronize()
             for k in ("rank", "kept", "R", "Q", "ratios"):
                 assert torch.equal(out[k], ref[k]), (threads, persistent, wgs, k)
 
 
-def test_batching_form_full_uneven_workload_sampled(rfm):
-    """The 64x64 uneven Helmholtz workload through one persistent launch: sampled blocks (the
+@pytest.mark.parametrize("algo", sorted(ALGOS))
+def test_batching_form_full_uneven_workload_sampled(rfm, algo):
+    """The 64x64 uneven Helmholtz workload in cost order (the direct form through one
+    persistent launch, the R-first form one workgroup per block): sampled blocks (the
     largest, the smallest, boundary and wide ones) against the oracle's filter."""
     inst = I.workload("helmholtz2d_uneven")
-    print("[batching] helmholtz2d_uneven full size", flush=True)
+    print(f"[batching] {algo} helmholtz2d_uneven full size", flush=True)
     plan, prob = _setup(rfm, inst)
     M, h = rfm.rfm_assemble(plan, prob)
     order = rfm.rfm_plan_order(plan)
-    tune = rfm.Tuning(rrqr_threads=1024, rrqr_persistent=1, rrqr_wgs_per_cu=1)
+    if algo == "direct":
+        tune = rfm.Tuning(rrqr_threads=1024, rrqr_persistent=1, rrqr_wgs_per_cu=1, rrqr_algo=rfm.RRQR_DIRECT)
+    else:
+        tune = rfm.Tuning(rrqr_algo=rfm.RRQR_RFIRST)
     out = rfm.rfm_rrqr_filter(plan, M, 1e-12, order=order, tune=tune)
     torch.cuda.synchronize()
     K = np.diff(inst.feat_off)
