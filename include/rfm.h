@@ -137,7 +137,9 @@ size_t rfm_rrqr_ws_bytes(const rfm_layout *L);
  * tau in [0, 1).  By default (max_cols <= 512) the pivoted factorisation runs on the
  * triangular factor R0 of an unpivoted QR M_j = Q0 R0, which has the same pivots, R and
  * Q = Q0 Q1 in exact arithmetic (R-first form); rfm_rrqr_filter_tuned can select the direct
- * factorisation of M_j.  The two give the same factors up to rounding.
+ * factorisation of M_j.  The two give the same factors up to rounding; identical columns of
+ * M_j have bit-equal norms only in the direct form (the R-first form keeps one of them, as
+ * rounding decides).
  * Inputs:  M device [nnz] (not modified).
  * Outputs: rank device [J]        r_j (0 <= r_j <= min(|I_j|, K_j));
  *          kept device [ncols]    kept local feature ids in pivot order, entries

@@ -40,6 +40,31 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wave through DPP row shifts and lane reads (no LDS traffic):
+// an inclusive scan within each row of 16 lanes (shifts by 1, 2, 4, 8; lanes without a
+// source add zero), then ((row0 + row1) + row2) + row3 from the rows' last lanes.  Every
+// lane receives the same value; the order of the additions is fixed.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row_shr(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_row_shr<0x111>(v);  // row_shr:1
+  v += dpp_row_shr<0x112>(v);  // row_shr:2
+  v += dpp_row_shr<0x114>(v);  // row_shr:4
+  v += dpp_row_shr<0x118>(v);  // row_shr:8
+  return ((lane_read(v, 15) + lane_read(v, 31)) + lane_read(v, 47)) + lane_read(v, 63);
+}
+
 // Sum over a workgroup of nthreads (multiple of 64) in a fixed order; result valid
 // in every thread.  scratch holds at least nthreads/64 doubles of LDS.
 __device__ __forceinline__ double block_sum(double v, double *scratch) {

@@ -61,8 +61,8 @@ __device__ __forceinline__ double reflect(double (&x)[TT], int r0, int s, int hi
     if (row == s) alpha = x[t];
     else if (row > s && row < hi) sig2 += x[t] * x[t];
   }
-  alpha = wave_sum(alpha);  // one non-zero term
-  sig2 = wave_sum(sig2);
+  alpha = wave_sum_dpp(alpha);  // one non-zero term
+  sig2 = wave_sum_dpp(sig2);
   if (sig2 == 0.0) {
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
@@ -100,7 +100,7 @@ __device__ __forceinline__ void apply_refl(double (&x)[G][TT], const double (&vr
     for (int t = 0; t < TT; ++t) f[g] += vr[t] * x[g][t];
   }
 #pragma unroll
-  for (int g = 0; g < G; ++g) f[g] = wave_sum(f[g]);
+  for (int g = 0; g < G; ++g) f[g] = wave_sum_dpp(f[g]);
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -112,7 +112,7 @@ __device__ __forceinline__ void apply_refl1(double (&x)[TT], const double (&vr)[
   double f = 0.0;
 #pragma unroll
   for (int t = 0; t < TT; ++t) f += vr[t] * x[t];
-  f = wave_sum(f);
+  f = wave_sum_dpp(f);
 #pragma unroll
   for (int t = 0; t < TT; ++t) x[t] -= th * (vr[t] * f);
 }
@@ -133,7 +133,7 @@ __device__ __forceinline__ void apply_refl_lds(double (&x)[G][TT], const double 
     for (int g = 0; g < G; ++g) f[g] += vv * x[g][t];
   }
 #pragma unroll
-  for (int g = 0; g < G; ++g) f[g] = wave_sum(f[g]);
+  for (int g = 0; g < G; ++g) f[g] = wave_sum_dpp(f[g]);
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
     const int rr = lane + kWave * t;
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
       xs[q][t] = ok ? A[(int64_t)c * m + row] : 0.0;
       ss += xs[q][t] * xs[q][t];
     }
-    ss = wave_sum(ss);
+    ss = wave_sum_dpp(ss);
     if (lane == 0) {
       sn[c] = (c < n) ? sqrt(ss) : -1.0;
       scol[c] = (c < n) ? c : -1;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
       dst[row] = a;
       ss += a * a;
     }
-    ss = wave_sum(ss);
+    ss = wave_sum_dpp(ss);
     if (lane == 0) {
       sn[c] = sqrt(ss);
       scol[c] = c;
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
 #pragma unroll
       for (int t = 0; t < TR; ++t)
         if (lane + kWave * t == s) dg = x[t];
-      dg = wave_sum(dg);
+      dg = wave_sum_dpp(dg);
       const double sg = (dg < 0.0) ? -1.0 : 1.0;
 #pragma unroll
       for (int t = 0; t < TR; ++t) {
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
         }
       }
 #pragma unroll
-      for (int u = 0; u < CH; ++u) f[u] = wave_sum(f[u]);
+      for (int u = 0; u < CH; ++u) f[u] = wave_sum_dpp(f[u]);
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         if (q0 + u < S) {
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
         }
       }
 #pragma unroll
-      for (int u = 0; u < CH; ++u) f[u] = wave_sum(f[u]);
+      for (int u = 0; u < CH; ++u) f[u] = wave_sum_dpp(f[u]);
       if (lane == 0) {
 #pragma unroll
         for (int u = 0; u < CH; ++u)
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
         for (int t = 0; t < TR; ++t) f[g] += vr[t] * x[g][t];
       }
 #pragma unroll
-      for (int g = 0; g < TB; ++g) f[g] = wave_sum(f[g]);
+      for (int g = 0; g < TB; ++g) f[g] = wave_sum_dpp(f[g]);
 #pragma unroll
       for (int g = 0; g < TB; ++g) {
         double ss = 0.0;
@@ -578,7 +578,7 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
         f[g] = ss;
       }
 #pragma unroll
-      for (int g = 0; g < TB; ++g) f[g] = wave_sum(f[g]);
+      for (int g = 0; g < TB; ++g) f[g] = wave_sum_dpp(f[g]);
 #pragma unroll
       for (int g = 0; g < TB; ++g) {
         if (col[g]) {
@@ -754,53 +754,86 @@ __global__ __launch_bounds__(NT) void rf_formq0(rfm_layout L, const int32_t *__r
 }
 
 // ---------------------------------------------------------------- Q_hat = Q0 Q1 D in place
-// Row tiles of RT rows of Q0 (nr columns) staged in LDS as tile[k * RT + row]; lane <-> row,
-// eight output columns per pass, Q1 entries broadcast from the W2 slot.
-template <int RT>
+// Row tiles of RT = 16384 / CP rows; every thread accumulates a 4 x 8 tile of the RT x CP
+// output (CP >= r) over slices of 16 of the nr inner indices staged in LDS (Q0 rows
+// As[k][row], Q1 rows Zs[k][q]).  The tile is written (times the sign normalisation) only
+// after its last slice, so the rows it overwrites have been read.
+template <int CP>
 __global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__restrict__ rank,
                                               double *__restrict__ Q, const double *__restrict__ W2,
                                               const double *__restrict__ dsgn, const int32_t *__restrict__ order) {
-  extern __shared__ double lds[];
-  constexpr int NS = kWave / RT;  // output groups per wave
-  constexpr int GQ = 8;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  const int row = lane % RT, sub = lane / RT;
-  {
-    const int j = order ? order[blockIdx.x] : blockIdx.x;
-    const Blk B = blk(L, j);
-    const int m = B.m, nr = B.nr, r = rank[j];
-    if (r == 0) return;
-    double *__restrict__ A = Q + B.base;
-    const double *__restrict__ Z = W2 + B.rsq;
-    for (int i0 = 0; i0 < m; i0 += RT) {
-      const int rows = min(RT, m - i0);
-      for (int e = tid; e < nr * RT; e += NT) {
-        const int k = e / RT, rr = e % RT;
-        lds[e] = (rr < rows) ? A[(int64_t)k * m + i0 + rr] : 0.0;
+  constexpr int RT = 16384 / CP, KC = 16, NC = CP / 8;
+  __shared__ double As[KC][RT];
+  __shared__ double Zs[KC][CP];
+  const int tid = threadIdx.x;
+  const int tc = tid % NC, tr = tid / NC;
+  const int j = order ? order[blockIdx.x] : blockIdx.x;
+  const Blk B = blk(L, j);
+  const int m = B.m, nr = B.nr, r = rank[j];
+  if (r == 0) return;
+  double *__restrict__ A = Q + B.base;
+  const double *__restrict__ Z = W2 + B.rsq;
+  for (int i0 = 0; i0 < m; i0 += RT) {
+    double acc[4][8];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+    // slices staged through registers: the loads of slice k0 + KC are in flight while
+    // slice k0 is multiplied
+    constexpr int NA = KC * RT / NT, NZ = KC * CP / NT;
+    double pa[NA], pz[NZ];
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        const int e = tid + u * NT, kk = e / RT, rr = e % RT;
+        pa[u] = (k0 + kk < nr && i0 + rr < m) ? A[(int64_t)(k0 + kk) * m + i0 + rr] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NZ; ++u) {
+        const int e = tid + u * NT, q = e / KC, kk = e % KC;
+        pz[u] = (k0 + kk < nr && q < r) ? Z[(int64_t)q * nr + k0 + kk] : 0.0;
+      }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < nr; k0 += KC) {
+#pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        const int e = tid + u * NT;
+        As[e / RT][e % RT] = pa[u];
+      }
+#pragma unroll
+      for (int u = 0; u < NZ; ++u) {
+        const int e = tid + u * NT;
+        Zs[e % KC][e / KC] = pz[u];
       }
       __syncthreads();
-      for (int q0 = (w * NS + sub) * GQ; q0 < r; q0 += NW * NS * GQ) {
-        double acc[GQ];
-        const double *zc[GQ];
+      if (k0 + KC < nr) fetch(k0 + KC);
+#pragma unroll 4
+      for (int kk = 0; kk < KC; ++kk) {
+        double av[4], zv[8];
 #pragma unroll
-        for (int g = 0; g < GQ; ++g) {
-          acc[g] = 0.0;
-          zc[g] = Z + (int64_t)min(q0 + g, r - 1) * nr;
-        }
-        for (int k = 0; k < nr; ++k) {
-          const double a = lds[k * RT + row];
+        for (int a = 0; a < 4; ++a) av[a] = As[kk][4 * tr + a];
 #pragma unroll
-          for (int g = 0; g < GQ; ++g) acc[g] += a * zc[g][k];
-        }
-        if (row < rows) {
+        for (int b = 0; b < 8; ++b) zv[b] = Zs[kk][8 * tc + b];
 #pragma unroll
-          for (int g = 0; g < GQ; ++g) {
-            const int q = q0 + g;
-            if (q < r) A[(int64_t)q * m + i0 + row] = dsgn[B.f0 + q] * acc[g];
-          }
-        }
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 8; ++b) acc[a][b] += av[a] * zv[b];
       }
       __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int q = 8 * tc + b;
+      if (q < r) {
+        const double sg = dsgn[B.f0 + q];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int row = i0 + 4 * tr + a;
+          if (row < m) A[(int64_t)q * m + row] = sg * acc[a][b];
+        }
+      }
     }
   }
 }
@@ -906,10 +939,10 @@ rfm_status launch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
 
 rfm_status dispatch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
   if (nr_max <= 64) return launch_small<1, 32, 8>(a, W, nr_max);
-  if (nr_max <= 128) return launch_small<2, 24, 8>(a, W, nr_max);
-  if (nr_max <= 256) return launch_small<4, 14, 4>(a, W, nr_max);
-  if (nr_max <= 320) return launch_small<5, 11, 4>(a, W, nr_max);
-  return launch_small<8, 6, 2>(a, W, nr_max);
+  if (nr_max <= 128) return launch_small<2, 28, 8>(a, W, nr_max);
+  if (nr_max <= 256) return launch_small<4, 18, 4>(a, W, nr_max);
+  if (nr_max <= 320) return launch_small<5, 13, 4>(a, W, nr_max);
+  return launch_small<8, 7, 2>(a, W, nr_max);
 }
 
 }  // namespace
@@ -939,17 +972,10 @@ rfm_status rrqr_rfirst(const RfirstArgs &a) {
   s = dispatch_tall(a, W, nb, false);
   if (s != RFM_OK) return s;
   const dim3 grid((unsigned)L->J);
-  const int RT = ((size_t)nr_max * 64 * sizeof(double) <= 140 * 1024) ? 64 : 32;
-  const size_t lds = (size_t)nr_max * RT * sizeof(double);
-  if (RT == 64) {
-    s = prep(rf_gemm<64>, lds);
-    if (s != RFM_OK) return s;
-    hipLaunchKernelGGL(rf_gemm<64>, grid, dim3(NT), lds, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
-  } else {
-    s = prep(rf_gemm<32>, lds);
-    if (s != RFM_OK) return s;
-    hipLaunchKernelGGL(rf_gemm<32>, grid, dim3(NT), lds, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
-  }
+  if (nr_max <= 256)
+    hipLaunchKernelGGL(rf_gemm<256>, grid, dim3(NT), 0, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
+  else
+    hipLaunchKernelGGL(rf_gemm<512>, grid, dim3(NT), 0, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
   RFM_LAUNCH_CHECK();
   return RFM_OK;
 }

@@ -185,7 +185,10 @@ def test_rrqr_edge_cases(rfm, algo):
     assert out["rank"][0] == 0 and out["rank"][4] == 0
     _compare_rrqr(plan, out, blocks, facts, np.diff(inst.feat_off), 1e-12)
     kept1 = out["kept"][plan.host["feat_off"][1]:plan.host["feat_off"][1] + out["rank"][1]]
-    assert 2 in kept1 and 7 not in kept1
+    if algo == "direct":   # bit-equal norms: the smaller feature id
+        assert 2 in kept1 and 7 not in kept1
+    else:                  # R0's two copies differ by rounding: exactly one of them is kept
+        assert (2 in kept1) != (7 in kept1)
 
 
 def _shared_factor_solve(rfm, inst, tau, atol, maxit=20000):
@@ -492,10 +495,13 @@ def test_lsqr_adjoint_tile_and_autotune(rfm):
         assert np.linalg.norm(y - ys[0]) <= 1e-7 * np.linalg.norm(ys[0])
     K = np.diff(inst.feat_off)
     M = _dev(H.pack_blocks(plan.host, blocks, K))
-    best, table, out = rfm.rfm_autotune(plan, M, 1e-10, hd, order=rfm.rfm_plan_order(plan), lsqr_iters=8)
-    assert best.rrqr_threads in (256, 512, 1024) and best.adj_tile in (16, 32, 64, 128, 256)
-    assert len(table) >= 6
-    ref = rfm.rfm_rrqr_filter(plan, M, 1e-10)
+    order = rfm.rfm_plan_order(plan)
+    best, table, out = rfm.rfm_autotune(plan, M, 1e-10, hd, order=order, lsqr_iters=8)
+    assert best.rrqr_algo in (rfm.RRQR_DIRECT, rfm.RRQR_RFIRST) and best.adj_tile in (16, 32, 64, 128, 256)
+    assert best.rrqr_algo == rfm.RRQR_RFIRST or best.rrqr_threads in (256, 512, 1024)
+    assert len(table) >= 7
+    # the outputs are those of the winning filter shape
+    ref = rfm.rfm_rrqr_filter(plan, M, 1e-10, order=order, tune=best)
     assert torch.equal(out["rank"], ref["rank"]) and torch.equal(out["Q"], ref["Q"])
 
 
