@@ -256,38 +256,66 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
 }
 
 // ---------------------------------------------------------------- pivoted QR of R0
-// Columns of R0 (rows 0..nr-1) live in slots: slot u < NREG is register slot u % S of wave
-// u / S, NREG <= u < NREG + nl is an LDS column, u >= NREG + nl is column u - NREG - nl of
-// the block's global slot W1 (ld nr).  Column c starts in slot c.  When the pivot comes
-// from a register or LDS slot, an active column of the global tier moves into the freed
-// slot, so the global tier drains as the factorisation proceeds.
+// One column per group of 16 lanes: lane i of a group holds rows i + 16 t (t < R16) of its
+// column, so the four groups of a wave work on four columns at once and each dot product is
+// a 16-lane reduction.  Columns of R0 (rows 0..nr-1) live in slots: slot u < NREG is a
+// register slot (group u % 4, index (u / 4) % S4, wave u / (4 S4)), NREG <= u < NREG + nl an
+// LDS column, u >= NREG + nl column u - NREG - nl of the block's part of W1 (K_j columns of
+// stride ld = 16 R16 from 16 R16 feat_off[j]; rows >= nr zero).  Column c starts in slot c.  When the pivot comes from a
+// register or LDS slot, an active column of the global tier moves into the freed slot, so
+// the global tier drains as the factorisation proceeds.
+// At step s every active column takes the reflector, gives up its row s (final: R entry
+// (s, column), kept in Rrow[column * n + s] of the block's slot W3) and has that row
+// cleared, so its norm below the pivot row is the norm of the whole stored column.
 // LDS: sn, scol [nslot] (norm, -1 once retired or empty; column id, -1 empty), t1, ds, perm
-// [nmax], glist, gpos (global slots still active, and where each sits in glist), vbuf, pcol
-// [64 TR], red/ired, regact [NW] (active register slots of each wave), then the LDS tier.
-__host__ __device__ constexpr size_t qrcp_small_bytes(int nmax, int nreg, int tr) {
-  return (size_t)(2 * nmax + (nmax + nreg) + 2 * kWave * tr + 32) * sizeof(double) +
+// [nmax], glist, gpos (global slots still active, and where each sits in glist), vabs [32 R16]
+// (the reflector by absolute row, zero outside [s, nr) and in its upper half), pcol [16 R16],
+// red/ired, regact [NW] (active register slots of each wave), then the LDS tier.
+// Register slots are kept aligned to the current window of 16 rows: entry t of lane i holds
+// row 16 (s / 16) + i + 16 t, the arrays shifting down by one entry every 16 steps, so row s
+// is always entry 0 of lane s % 16 and no row test is needed in the inner loops.
+__host__ __device__ constexpr size_t qrcp_small_bytes(int nmax, int nreg, int r16) {
+  return (size_t)(2 * nmax + (nmax + nreg) + 3 * 16 * r16 + 32) * sizeof(double) +
          (size_t)(2 * (nmax + nreg) + 2 * nmax + 64 + NW + 2) * sizeof(int) + 8;
 }
 
-template <int TR, int S>
+// Sum over each group of 16 lanes (a DPP row) by a rotate butterfly: every lane of the row
+// receives the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_row<0x128>(v);  // row_ror:8
+  v += dpp_row<0x124>(v);  // row_ror:4
+  v += dpp_row<0x122>(v);  // row_ror:2
+  v += dpp_row<0x121>(v);  // row_ror:1
+  return v;
+}
+
+template <int R16, int S4>
 __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__restrict__ Q, double tau,
                                               int32_t *__restrict__ rank_out, int32_t *__restrict__ kept,
                                               double *__restrict__ Rout, double *__restrict__ ratios,
                                               double *__restrict__ tau1, double *__restrict__ dsgn,
-                                              double *__restrict__ W1, int64_t tier_doubles,
-                                              const int32_t *__restrict__ order) {
+                                              double *__restrict__ W1, double *__restrict__ W3,
+                                              int64_t tier_doubles, const int32_t *__restrict__ order) {
   extern __shared__ double lds[];
-  constexpr int NREG = NW * S;
-  constexpr int CH = S < 8 ? S : 8;
-  constexpr int TB = TR <= 2 ? 4 : 2;
+  constexpr int TR = R16 / 4;       // rows per lane in the 64-lane layout of the reflector
+  constexpr int NREG = NW * S4 * 4;
+  constexpr int LD = 16 * R16;      // stride of LDS and global tier columns
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int li = lane & 15, qd = lane >> 4;
   const int nmax = L.max_cols, nsl = nmax + NREG;
   double *sn = lds;                  // [nsl]
   double *t1 = sn + nsl;             // [nmax]
   double *ds = t1 + nmax;            // [nmax]
-  double *vbuf = ds + nmax;          // [64 TR]
-  double *pcol = vbuf + kWave * TR;  // [64 TR]
-  double *red = pcol + kWave * TR;   // [32]
+  double *vabs = ds + nmax;          // [2 * 16 R16] reflector by absolute row, zero elsewhere
+  double *pcol = vabs + 2 * LD;      // [16 R16]
+  double *red = pcol + LD;           // [32]
   int *scol = (int *)(red + 32);     // [nsl]
   int *gpos = scol + nsl;            // [nsl]
   int *perm = gpos + nsl;            // [nmax]
@@ -302,94 +330,113 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
   const int m = B.m, n = B.n, nr = B.nr;
   const double *__restrict__ A = Q + B.base;
   double *__restrict__ R = Rout + B.rsq;
-  double *__restrict__ Wg = W1 + B.rsq;
-  const int nl = (nr > 0) ? (int)min((int64_t)max(n - NREG, 0), tier_doubles / nr) : 0;
-  const int gbase = NREG + nl;        // first global slot
-  const int nslot = max(n, NREG);     // slots in use
+  double *__restrict__ Wg = W1 + B.f0 * LD;
+  double *__restrict__ Rrow = W3 + B.rsq;
+  const int nl = (nr > 0) ? (int)min((int64_t)max(n - NREG, 0), tier_doubles / LD) : 0;
+  const int gbase = NREG + nl;
+  const int nslot = max(n, NREG);
+  auto colptr = [&](int u) -> double * {
+    return (u < gbase) ? tier + (int64_t)(u - NREG) * LD : Wg + (int64_t)(u - gbase) * LD;
+  };
 
-  // ---- R0 (upper triangle of the factored block) into the tiers, initial norms
-  double xs[S][TR];
+  // Every lane tracks the best (norm, column, slot) among the columns its group of 16 lanes
+  // (or its wave, in the 64-lane loops) has just normed; a wave's best goes to red/ired.
+  double bn = -0.5;
+  int bc = 0x7fffffff, bs = -1;
+  auto track = [&](double v, int c, int u) {
+    if (v > bn || (v == bn && c < bc)) {
+      bn = v;
+      bc = c;
+      bs = u;
+    }
+  };
+  auto publish = [&]() {  // combine the four groups of the wave; lane 0 writes
 #pragma unroll
-  for (int q = 0; q < S; ++q) {
-    const int c = w * S + q;
+    for (int off = 16; off < kWave; off <<= 1) {
+      const double ob = __shfl_xor(bn, off, kWave);
+      const int oc = __shfl_xor(bc, off, kWave);
+      const int ou = __shfl_xor(bs, off, kWave);
+      if (ob > bn || (ob == bn && oc < bc)) {
+        bn = ob;
+        bc = oc;
+        bs = ou;
+      }
+    }
+    if (lane == 0) {
+      red[w] = bn;
+      ired[w] = bc;
+      ired[32 + w] = bs;
+    }
+    bn = -0.5;
+    bc = 0x7fffffff;
+    bs = -1;
+  };
+
+  // ---- R0 into the tiers (rows >= nr zero), initial norms
+  double xs[S4][R16];
+#pragma unroll
+  for (int q = 0; q < S4; ++q) {
+    const int c = (w * S4 + q) * 4 + qd;
     double ss = 0.0;
 #pragma unroll
-    for (int t = 0; t < TR; ++t) {
-      const int row = lane + kWave * t;
+    for (int t = 0; t < R16; ++t) {
+      const int row = li + 16 * t;
       const bool ok = c < n && row < nr && row <= c;
       xs[q][t] = ok ? A[(int64_t)c * m + row] : 0.0;
       ss += xs[q][t] * xs[q][t];
     }
-    ss = wave_sum_dpp(ss);
-    if (lane == 0) {
+    ss = row16_sum(ss);
+    if (c < n) track(sqrt(ss), c, c);
+    if (li == 0) {
       sn[c] = (c < n) ? sqrt(ss) : -1.0;
       scol[c] = (c < n) ? c : -1;
     }
   }
   for (int c = NREG + w; c < n; c += NW) {
     double ss = 0.0;
-    double *dst = (c < gbase) ? tier + (int64_t)(c - NREG) * nr : Wg + (int64_t)(c - gbase) * nr;
-    for (int row = lane; row < nr; row += kWave) {
-      const double a = (row <= c) ? A[(int64_t)c * m + row] : 0.0;
+    double *dst = colptr(c);
+    for (int row = lane; row < LD; row += kWave) {
+      const double a = (row <= c && row < nr) ? A[(int64_t)c * m + row] : 0.0;
       dst[row] = a;
       ss += a * a;
     }
     ss = wave_sum_dpp(ss);
+    track(sqrt(ss), c, c);
     if (lane == 0) {
       sn[c] = sqrt(ss);
       scol[c] = c;
     }
   }
+  publish();
   for (int u = gbase + tid; u < n; u += NT) {
     glist[u - gbase] = u;
     gpos[u] = u - gbase;
   }
   if (tid < NW) {
     unsigned bits = 0;
-    for (int q = 0; q < S; ++q)
-      if (tid * S + q < n) bits |= 1u << q;
+    for (int b = 0; b < 4 * S4; ++b)
+      if ((tid * S4 + b / 4) * 4 + b % 4 < n) bits |= 1u << b;
     regact[tid] = bits;
   }
   if (tid == 0) gcnt[0] = max(n - gbase, 0);
   if (ratios)
     for (int c = tid; c < n; c += NT) ratios[B.f0 + c] = 0.0;
+  for (int row = tid; row < 2 * LD; row += NT) vabs[row] = 0.0;
   __syncthreads();
 
   int r = nr;
   double ref = 0.0;
   for (int s = 0; s < nr; ++s) {
-    // ---- pivot: largest trailing norm, ties to the smallest column
-    double best = -0.5;
-    int bid = 0x7fffffff, bu = -1;
-    for (int u = tid; u < nslot; u += NT) {
-      const double cv = sn[u];
-      const int c = scol[u];
-      if (cv > best || (cv == best && c < bid)) {
-        best = cv;
-        bid = c;
-        bu = u;
-      }
-    }
+    const int ts = s >> 4, ls = s & 15;
+    if (s > 0 && ls == 0) {  // the register window moves down 16 rows
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, kWave);
-      const int oid = __shfl_xor(bid, off, kWave);
-      const int ou = __shfl_xor(bu, off, kWave);
-      if (ob > best || (ob == best && oid < bid)) {
-        best = ob;
-        bid = oid;
-        bu = ou;
-      }
+      for (int q = 0; q < S4; ++q)
+#pragma unroll
+        for (int t = 0; t < R16; ++t) xs[q][t] = (t + 1 < R16) ? xs[q][t + 1] : 0.0;
     }
-    if (lane == 0) {
-      red[w] = best;
-      ired[w] = bid;
-      ired[32 + w] = bu;
-    }
-    __syncthreads();
-    best = red[0];
-    bid = ired[0];
-    bu = ired[32];
+    // ---- pivot: the best of the waves' bests (largest norm, ties to the smallest column)
+    double best = red[0];
+    int bid = ired[0], bu = ired[32];
     for (int ww = 1; ww < NW; ++ww) {
       const double ob = red[ww];
       const int oid = ired[ww];
@@ -411,27 +458,32 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
     }
     const int P = bid, U = bu;
 
-    // ---- the pivot column to LDS by the wave that holds it; a global column refills the slot
-    const int owner = (U < NREG) ? U / S : 0;
+    // ---- the pivot column to LDS (absolute rows) by the wave that holds it; a global
+    // column refills the slot
+    const int owner = (U < NREG) ? U / (4 * S4) : 0;
     if (w == owner) {
       const int gc = gcnt[0];
       const int g = (U < gbase && gc > 0) ? glist[gc - 1] : -1;
-      const double *gsrc = (g >= 0) ? Wg + (int64_t)(g - gbase) * nr : nullptr;
+      const double *gsrc = (g >= 0) ? colptr(g) : nullptr;
       if (U < NREG) {
-        const int qp = U - owner * S;
+        const int qp = (U / 4) % S4, qq = U % 4;
+        if (qd == qq) {
 #pragma unroll
-        for (int q = 0; q < S; ++q)
-          if (q == qp) {
+          for (int q = 0; q < S4; ++q)
+            if (q == qp) {
 #pragma unroll
-            for (int t = 0; t < TR; ++t) {
-              const int row = lane + kWave * t;
-              if (row < nr) pcol[row] = xs[q][t];
-              if (gsrc) xs[q][t] = (row < nr) ? gsrc[row] : 0.0;
+              for (int t = 0; t < R16; ++t) {
+                if (t + ts < R16) {
+                  const int row = 16 * ts + li + 16 * t;
+                  pcol[row] = xs[q][t];
+                  if (gsrc) xs[q][t] = gsrc[row];
+                }
+              }
             }
-          }
+        }
       } else {
-        double *src = (U < gbase) ? tier + (int64_t)(U - NREG) * nr : Wg + (int64_t)(U - gbase) * nr;
-        for (int row = lane; row < nr; row += kWave) {
+        double *src = colptr(U);
+        for (int row = lane; row < LD; row += kWave) {
           pcol[row] = src[row];
           if (gsrc) src[row] = gsrc[row];
         }
@@ -447,7 +499,7 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
         } else {
           sn[U] = -1.0;
           scol[U] = -1;
-          if (U < NREG) regact[owner] &= ~(1u << (U - owner * S));
+          if (U < NREG) regact[owner] &= ~(1u << (U - owner * 4 * S4));
           if (U >= gbase) {  // swap-remove U from glist
             const int k = gpos[U], last = glist[gc - 1];
             glist[k] = last;
@@ -457,140 +509,122 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
         }
       }
     }
-    __syncthreads();  // pcol complete; everyone has read red/ired
+    __syncthreads();
 
-    // ---- reflector (wave 0); column s of the R slot: R_hat entries with normalised signs
-    // on and above the diagonal, the reflector below it
+    // ---- reflector (wave 0, 64-lane layout) into vabs
     if (w == 0) {
       double x[TR];
 #pragma unroll
-      for (int t = 0; t < TR; ++t) {
-        const int row = lane + kWave * t;
-        x[t] = (row < nr) ? pcol[row] : 0.0;
-      }
-      const double th = reflect<TR>(x, 0, s, nr, vbuf);
+      for (int t = 0; t < TR; ++t) x[t] = pcol[lane + kWave * t];
+      const double th = reflect<TR>(x, 0, s, nr, vabs + s);
       double dg = 0.0;
 #pragma unroll
-      for (int t = 0; t < TR; ++t)
-        if (lane + kWave * t == s) dg = x[t];
-      dg = wave_sum_dpp(dg);
-      const double sg = (dg < 0.0) ? -1.0 : 1.0;
-#pragma unroll
       for (int t = 0; t < TR; ++t) {
         const int row = lane + kWave * t;
-        if (row < nr) R[(int64_t)s * n + row] = (row < s) ? ds[row] * x[t] : (row == s) ? sg * x[t] : x[t];
+        if (row == s) dg = x[t];
+        if (row < s || row >= nr) vabs[row] = 0.0;
       }
+      dg = wave_sum_dpp(dg);
       if (lane == 0) {
         t1[s] = th;
-        ds[s] = sg;
+        ds[s] = (dg < 0.0) ? -1.0 : 1.0;
+        red[16] = dg;
       }
     }
     __syncthreads();
 
-    // ---- every active column takes the reflector; norms recomputed from the new entries
+    // ---- column s of the R slot (last wave): the pivot column's R entries from Rrow and its
+    // diagonal with normalised signs, the reflector below
+    if (w == NW - 1) {
+      const double dg = red[16];
+      for (int row = lane; row < nr; row += kWave)
+        R[(int64_t)s * n + row] = (row < s) ? ds[row] * Rrow[(int64_t)P * n + row]
+                                            : (row == s) ? ds[s] * dg : vabs[row];
+    }
+
+    // ---- every active column takes the reflector, gives up row s (entry 0 of lane s % 16),
+    // and has its norm recomputed from its entries below the pivot row
     const double th = t1[s];
-    double vr[TR];
+    double vr[R16];
 #pragma unroll
-    for (int t = 0; t < TR; ++t) {
-      const int row = lane + kWave * t;
-      vr[t] = (row >= s && row < nr) ? vbuf[row - s] : 0.0;
-    }
-    // register tier, CH slots at a time (their reductions overlap)
-    const unsigned act = regact[w];
+    for (int t = 0; t < R16; ++t) vr[t] = vabs[16 * ts + li + 16 * t];
+    {
+      const unsigned act = regact[w];
+      double f[S4];
 #pragma unroll
-    for (int q0 = 0; q0 < S; q0 += CH) {
-      double f[CH];
+      for (int q = 0; q < S4; ++q) {
+        f[q] = 0.0;
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        f[u] = 0.0;
-        if (q0 + u < S) {
-#pragma unroll
-          for (int t = 0; t < TR; ++t) f[u] += vr[t] * xs[q0 + u][t];
-        }
+        for (int t = 0; t < R16; ++t) f[q] = fma(vr[t], xs[q][t], f[q]);
       }
 #pragma unroll
-      for (int u = 0; u < CH; ++u) f[u] = wave_sum_dpp(f[u]);
+      for (int q = 0; q < S4; ++q) f[q] = row16_sum(f[q]);
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        if (q0 + u < S) {
-          const double sc = ((act >> (q0 + u)) & 1u) ? th : 0.0;
-          double ss = 0.0;
+      for (int q = 0; q < S4; ++q) {
+        const bool on = (act >> (4 * q + qd)) & 1u;
+        const double g = on ? -th * f[q] : 0.0;
 #pragma unroll
-          for (int t = 0; t < TR; ++t) {
-            xs[q0 + u][t] -= sc * (vr[t] * f[u]);
-            const int row = lane + kWave * t;
-            const double xv = (row > s && row < nr) ? xs[q0 + u][t] : 0.0;
-            ss += xv * xv;
-          }
-          f[u] = ss;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < CH; ++u) f[u] = wave_sum_dpp(f[u]);
-      if (lane == 0) {
-#pragma unroll
-        for (int u = 0; u < CH; ++u)
-          if (q0 + u < S && ((act >> (q0 + u)) & 1u)) sn[w * S + q0 + u] = sqrt(f[u]);
-      }
-    }
-    // LDS tier, then the global tier (by glist), TB columns per wave at a time
-    const int gc = gcnt[0];
-    const int nother = nl + gc;
-    for (int k0 = TB * w; k0 < nother; k0 += TB * NW) {
-      double x[TB][TR], sc[TB];
-      double *col[TB];
-      int us[TB];
-#pragma unroll
-      for (int g = 0; g < TB; ++g) {
-        const int k = k0 + g;
-        int u = -1;
-        if (k < nl) u = NREG + k;
-        else if (k < nother) u = glist[k - nl];
-        const bool live = u >= 0 && sn[u] >= 0.0;
-        us[g] = live ? u : -1;
-        sc[g] = live ? th : 0.0;
-        col[g] = !live ? nullptr : (u < gbase) ? tier + (int64_t)(u - NREG) * nr : Wg + (int64_t)(u - gbase) * nr;
-#pragma unroll
-        for (int t = 0; t < TR; ++t) {
-          const int row = lane + kWave * t;
-          x[g][t] = (live && row >= s && row < nr) ? col[g][row] : 0.0;
-        }
-      }
-      double f[TB];
-#pragma unroll
-      for (int g = 0; g < TB; ++g) {
-        f[g] = 0.0;
-#pragma unroll
-        for (int t = 0; t < TR; ++t) f[g] += vr[t] * x[g][t];
-      }
-#pragma unroll
-      for (int g = 0; g < TB; ++g) f[g] = wave_sum_dpp(f[g]);
-#pragma unroll
-      for (int g = 0; g < TB; ++g) {
+        for (int t = 0; t < R16; ++t) xs[q][t] = fma(g, vr[t], xs[q][t]);
+        const double ext = xs[q][0];
+        if (li == ls) xs[q][0] = 0.0;
         double ss = 0.0;
 #pragma unroll
-        for (int t = 0; t < TR; ++t) {
-          x[g][t] -= sc[g] * (vr[t] * f[g]);
-          const int row = lane + kWave * t;
-          const double xv = (row > s && row < nr) ? x[g][t] : 0.0;
-          ss += xv * xv;
-        }
-        f[g] = ss;
+        for (int t = 0; t < R16; ++t) ss = fma(xs[q][t], xs[q][t], ss);
+        f[q] = ss;
+        if (on && li == ls) Rrow[(int64_t)scol[(w * S4 + q) * 4 + qd] * n + s] = ext;
       }
 #pragma unroll
-      for (int g = 0; g < TB; ++g) f[g] = wave_sum_dpp(f[g]);
+      for (int q = 0; q < S4; ++q) f[q] = row16_sum(f[q]);
 #pragma unroll
-      for (int g = 0; g < TB; ++g) {
-        if (col[g]) {
-#pragma unroll
-          for (int t = 0; t < TR; ++t) {
-            const int row = lane + kWave * t;
-            if (row >= s && row < nr) col[g][row] = x[g][t];
-          }
-          if (lane == 0) sn[us[g]] = sqrt(f[g]);
+      for (int q = 0; q < S4; ++q) {
+        if ((act >> (4 * q + qd)) & 1u) {
+          const int u = (w * S4 + q) * 4 + qd;
+          const double nv = sqrt(f[q]);
+          track(nv, scol[u], u);
+          if (li == 0) sn[u] = nv;
         }
       }
     }
+    // LDS tier, then the global tier (by glist): one column per group of 16 lanes, loaded
+    // into the same window layout; rows below the window are zero in storage and are
+    // neither read nor written
+    for (int k0 = 4 * w; k0 < nl + gcnt[0]; k0 += 4 * NW) {
+      const int kk = k0 + qd;
+      const int gcv = gcnt[0];
+      int u = -1;
+      if (kk < nl) u = NREG + kk;
+      else if (kk < nl + gcv) u = glist[kk - nl];
+      const bool live = u >= 0 && sn[u] >= 0.0;
+      double *col = live ? colptr(u) : pcol;  // a dead group reads pcol and writes nothing
+      double x[R16];
+      double f = 0.0;
+#pragma unroll
+      for (int t = 0; t < R16; ++t) {
+        x[t] = (t + ts < R16) ? col[16 * ts + li + 16 * t] : 0.0;
+        f = fma(vr[t], x[t], f);
+      }
+      f = row16_sum(f);
+      const double g = live ? -th * f : 0.0;
+#pragma unroll
+      for (int t = 0; t < R16; ++t) x[t] = fma(g, vr[t], x[t]);
+      const double ext = x[0];
+      if (li == ls) x[0] = 0.0;
+      double ss = 0.0;
+#pragma unroll
+      for (int t = 0; t < R16; ++t) ss = fma(x[t], x[t], ss);
+      ss = row16_sum(ss);
+      if (live) {
+#pragma unroll
+        for (int t = 0; t < R16; ++t)
+          if (t + ts < R16) col[16 * ts + li + 16 * t] = x[t];
+        const int c = scol[u];
+        const double nv = sqrt(ss);
+        track(nv, c, u);
+        if (li == ls) Rrow[(int64_t)c * n + s] = ext;
+        if (li == 0) sn[u] = nv;
+      }
+    }
+    publish();
     __syncthreads();
   }
 
@@ -841,8 +875,13 @@ __global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__res
 size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Ws {
-  double *tau0, *tau1, *dsgn, *W1, *W2;
+  double *tau0, *tau1, *dsgn, *W1, *W2, *W3;
 };
+
+// Rows per lane of the pivoted QR's 16-lane layout for blocks of up to nr_max rows of R0.
+int r16_of(int nr_max) { return nr_max <= 64 ? 4 : nr_max <= 128 ? 8 : nr_max <= 256 ? 16 : nr_max <= 320 ? 20 : 32; }
+
+int nr_max_of(const rfm_layout *L) { return std::max(1, std::min(L->max_rows, L->max_cols)); }
 
 size_t carve(const rfm_layout *L, char *base, Ws *W) {
   size_t off = 0;
@@ -856,8 +895,9 @@ size_t carve(const rfm_layout *L, char *base, Ws *W) {
   w.tau0 = (double *)take(nc * sizeof(double));
   w.tau1 = (double *)take(nc * sizeof(double));
   w.dsgn = (double *)take(nc * sizeof(double));
-  w.W1 = (double *)take(nq * sizeof(double));
+  w.W1 = (double *)take(nc * 16 * (size_t)r16_of(nr_max_of(L)) * sizeof(double));
   w.W2 = (double *)take(nq * sizeof(double));
+  w.W3 = (double *)take(nq * sizeof(double));
   if (W) *W = w;
   return off;
 }
@@ -906,23 +946,25 @@ rfm_status dispatch_tall(const RfirstArgs &a, const Ws &W, int nb, bool first) {
   return launch_tall<48>(a, W, nb, first);
 }
 
-template <int TR, int S, int GQ1>
+template <int R16, int S4, int GQ1>
 rfm_status launch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
+  constexpr int TR = R16 / 4;
   const rfm_layout *L = a.L;
   const dim3 grid((unsigned)L->J);
   const int nmax = L->max_cols;
-  const size_t small = qrcp_small_bytes(nmax, NW * S, TR);
-  const int64_t want = (int64_t)std::max(0, nmax - NW * S) * nr_max;
+  const int nreg = NW * S4 * 4;
+  const size_t small = qrcp_small_bytes(nmax, nreg, R16);
+  const int64_t want = (int64_t)std::max(0, nmax - nreg) * 16 * R16;
   int64_t tier = (int64_t)((kLdsCap - small) / sizeof(double));
   if (tier > want) tier = want;
   if (tier < 0) tier = 0;
   const size_t lds = small + (size_t)tier * sizeof(double);
   {
-    auto kern = rf_qrcp<TR, S>;
+    auto kern = rf_qrcp<R16, S4>;
     rfm_status s = prep(kern, lds);
     if (s != RFM_OK) return s;
     hipLaunchKernelGGL(kern, grid, dim3(NT), lds, a.st, *L, (const double *)a.Q, a.tau, a.rank, a.kept, a.R,
-                       a.ratios, W.tau1, W.dsgn, W.W1, tier, a.order);
+                       a.ratios, W.tau1, W.dsgn, W.W1, W.W3, tier, a.order);
     RFM_LAUNCH_CHECK();
   }
   {
@@ -938,11 +980,13 @@ rfm_status launch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
 }
 
 rfm_status dispatch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
-  if (nr_max <= 64) return launch_small<1, 32, 8>(a, W, nr_max);
-  if (nr_max <= 128) return launch_small<2, 28, 8>(a, W, nr_max);
-  if (nr_max <= 256) return launch_small<4, 18, 4>(a, W, nr_max);
-  if (nr_max <= 320) return launch_small<5, 13, 4>(a, W, nr_max);
-  return launch_small<8, 7, 2>(a, W, nr_max);
+  switch (r16_of(nr_max)) {
+    case 4: return launch_small<4, 8, 8>(a, W, nr_max);
+    case 8: return launch_small<8, 8, 8>(a, W, nr_max);
+    case 16: return launch_small<16, 4, 4>(a, W, nr_max);
+    case 20: return launch_small<20, 3, 4>(a, W, nr_max);
+    default: return launch_small<32, 1, 2>(a, W, nr_max);
+  }
 }
 
 }  // namespace
@@ -959,7 +1003,7 @@ rfm_status rrqr_rfirst(const RfirstArgs &a) {
   if (L->J < 1) return RFM_OK;
   Ws W;
   carve(L, (char *)a.ws, &W);
-  const int nr_max = std::max(1, std::min(L->max_rows, L->max_cols));
+  const int nr_max = nr_max_of(L);
   const int mr = std::max(1, L->max_rows);
   // panel width of the tall passes: nb reflectors of max_rows entries in LDS, at most the
   // panel columns the waves hold in registers
