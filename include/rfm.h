@@ -134,7 +134,7 @@ size_t rfm_rrqr_ws_bytes(const rfm_layout *L);
  * orthogonal to the columns already chosen, the norms recomputed exactly from the updated
  * columns; bit-equal norms go to the smallest local feature id), stopping at the first
  * step s with |R_ss| <= tau * |R_00| (threshold relative to the leading diagonal of R_j).
- * tau in [0, 1).  By default (max_cols <= 512) the pivoted factorisation runs on the
+ * tau in [0, 1).  By default (64 < max_cols <= 512) the pivoted factorisation runs on the
  * triangular factor R0 of an unpivoted QR M_j = Q0 R0, which has the same pivots, R and
  * Q = Q0 Q1 in exact arithmetic (R-first form); rfm_rrqr_filter_tuned can select the direct
  * factorisation of M_j.  The two give the same factors up to rounding; identical columns of
@@ -172,7 +172,7 @@ typedef struct {
 } rfm_tuning;
 
 typedef enum {
-  RFM_RRQR_AUTO = 0,   /* R-first when max_cols <= 512, else direct */
+  RFM_RRQR_AUTO = 0,   /* R-first when 64 < max_cols <= 512, else direct */
   RFM_RRQR_DIRECT = 1, /* pivoted QR of M_j itself (rrqr_threads applies) */
   RFM_RRQR_RFIRST = 2  /* pivoted QR of R0 from an unpivoted QR of M_j */
 } rfm_rrqr_algo;

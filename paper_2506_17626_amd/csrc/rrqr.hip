@@ -429,7 +429,9 @@ extern "C" rfm_status rfm_rrqr_filter_tuned(const rfm_layout *L, const double *M
     return fail(RFM_EINVAL, "rfm_rrqr_filter: rrqr_algo must be RFM_RRQR_AUTO, _DIRECT or _RFIRST");
   if (algo == RFM_RRQR_RFIRST && persistent)
     return fail(RFM_EINVAL, "rfm_rrqr_filter: the persistent launch belongs to the direct form");
-  if (algo == RFM_RRQR_RFIRST || (algo == RFM_RRQR_AUTO && !persistent && rfirst_supported(L))) {
+  // by default the R-first form, except for narrow blocks (at most 64 features), where the
+  // direct form's single launch is faster than five
+  if (algo == RFM_RRQR_RFIRST || (algo == RFM_RRQR_AUTO && !persistent && L->max_cols > 64 && rfirst_supported(L))) {
     RfirstArgs ra{L, M, tau, rank, kept, R, Q, ratios, order, ws, ws_bytes, (hipStream_t)stream};
     return rrqr_rfirst(ra);
   }

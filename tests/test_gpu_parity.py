@@ -432,7 +432,7 @@ def test_batching_form_results_independent_of_order_and_launch_shape(rfm):
     K = np.diff(inst.feat_off)
     M = _dev(H.pack_blocks(plan.host, blocks, K))
     order = rfm.rfm_plan_order(plan)
-    ref = rfm.rfm_rrqr_filter(plan, M, 1e-12)
+    ref = rfm.rfm_rrqr_filter(plan, M, 1e-12, tune=rfm.Tuning(rrqr_algo=rfm.RRQR_RFIRST))
     out = rfm.rfm_rrqr_filter(plan, M, 1e-12, order=order, tune=rfm.Tuning(rrqr_algo=rfm.RRQR_RFIRST))
     torch.cuda.synchronize()
     for k in ("rank", "kept", "R", "Q", "ratios"):
