@@ -10,8 +10,9 @@
 //   fwd_gather  p_r = sum_{j covering r} t_(j,r) - alpha u_r, summed in ascending j (no
 //               atomics, so the result does not depend on scheduling); ||p||^2 partials
 //               -> reduce_step: beta
-//   adj_local   z_j = Q_hat_j^T (p / beta) over column tiles of I_j x r_j (rows gathered to
-//               LDS once per workgroup), q = z - beta v; ||q||^2 partials
+//   adj_local   z_j = Q_hat_j^T (p / beta) over column tiles of I_j x r_j (the block's rows
+//               of p, copied contiguously by fwd_gather, staged in LDS once per
+//               workgroup), q = z - beta v; ||q||^2 partials
 //               -> reduce_step: alpha and the Givens-rotation scalar step of Paige-Saunders
 //   yw_update   y += (phi/rho) w, w = v - (theta/rho) w; ||y||^2 partials
 //               -> reduce_step: ||y|| and the stopping rule (raises the done flag)
@@ -113,37 +114,38 @@ __global__ __launch_bounds__(kRowTile) void fwd_local(rfm_layout L, const T *__r
   const int i = blockIdx.x * kRowTile + threadIdx.x;
   if (i >= m) return;
   const int64_t base = L.blk_off[j] + i;
-  A acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+  // eight independent accumulators: eight loads in flight per thread
+  A acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int k = 0;
-  for (; k + 4 <= r; k += 4) {
-    acc0 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k, m)) * vs[k];
-    acc1 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k + 1, m)) * vs[k + 1];
-    acc2 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k + 2, m)) * vs[k + 2];
-    acc3 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k + 3, m)) * vs[k + 3];
+  for (; k + 8 <= r; k += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k + u, m)) * vs[k + u];
   }
-  for (; k < r; ++k) acc0 += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k, m)) * vs[k];
-  t[r0 + i] = (double)((acc0 + acc1) + (acc2 + acc3));
+  for (; k < r; ++k) acc[0] += (A)widen(*operand_col<T, KEPT>(Op, base, ks, k, m)) * vs[k];
+  t[r0 + i] = (double)(((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
 }
 
 // p_r = sum_j t_(j,r) - alpha * (pcur_r / beta)     (ITER)
 // p_r = h_r - sum_j t_(j,r)                         (RESID)
 // p_r = h_r                                         (COPYH)
-// Per-workgroup partial sums of p^2 (and of h^2 outside ITER) go to part[] / part2[].
+// p goes to pnew (row order) and to ub in the block-row layout of t (ub[e] = p_rows[e]), so
+// the adjoint products read their rows contiguously.  Per-workgroup partial sums of p^2 (and
+// of h^2 outside ITER) go to part[] / part2[].
 __global__ __launch_bounds__(kVecThreads) void fwd_gather(rfm_layout L, const double *__restrict__ t,
                                                           const double *__restrict__ h,
                                                           const double *__restrict__ pcur,
-                                                          double *__restrict__ pnew, double *part,
-                                                          double *part2, const State *st, int mode) {
+                                                          double *__restrict__ pnew, double *__restrict__ ub,
+                                                          double *part, double *part2, const State *st,
+                                                          int mode) {
   __shared__ double red[kVecThreads / kWave];
   if (mode == ITER && st->done) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double val = 0.0, hh = 0.0;
   if (r < L.N) {
     double s = 0.0;
-    if (mode != COPYH) {
-      const int64_t q1 = L.rinc_off[r + 1];
-      for (int64_t q = L.rinc_off[r]; q < q1; ++q) s += t[L.rinc[q]];
-    }
+    const int64_t q0 = L.rinc_off[r], q1 = L.rinc_off[r + 1];
+    if (mode != COPYH)
+      for (int64_t q = q0; q < q1; ++q) s += t[L.rinc[q]];
     if (mode == ITER) {
       val = s - st->alpha * (pcur[r] / st->beta);
     } else {
@@ -152,6 +154,7 @@ __global__ __launch_bounds__(kVecThreads) void fwd_gather(rfm_layout L, const do
       hh = hr * hr;
     }
     pnew[r] = val;
+    for (int64_t q = q0; q < q1; ++q) ub[L.rinc[q]] = val;
   }
   const double bs = block_sum(val * val, red);
   if (threadIdx.x == 0) part[blockIdx.x] = bs;
@@ -161,15 +164,16 @@ __global__ __launch_bounds__(kVecThreads) void fwd_gather(rfm_layout L, const do
   }
 }
 
-// z_j = Op_j^T u_{I_j} over a tile of ct columns of block j, u = pnew / beta_next
-// (F_DIV_BETA) or pnew; with F_COMBINE q = z - beta_next * (qcur / alpha), else q = z.
-// Each wave takes 4 columns at a time; the block's residual rows are gathered to LDS once
-// per workgroup.  One partial of sum q^2 per workgroup.
+// z_j = Op_j^T u_{I_j} over a tile of ct columns of block j, u = p / beta_next (F_DIV_BETA)
+// or p, with p in the block-row layout (ub, written by fwd_gather); with F_COMBINE
+// q = z - beta_next * (qcur / alpha), else q = z.  Each wave takes 4 columns at a time; the
+// block's rows of u are staged in LDS once per workgroup.  One partial of sum q^2 per
+// workgroup.
 template <typename T, bool KEPT>
 __global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const T *__restrict__ Op,
                                                          const int32_t *__restrict__ kept,
                                                          const int32_t *__restrict__ rank,
-                                                         const double *__restrict__ pnew,
+                                                         const double *__restrict__ ub,
                                                          const double *__restrict__ qcur,
                                                          double *__restrict__ qnew, double *part,
                                                          int ct, const State *st, int flags) {
@@ -197,7 +201,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const T *
   A *us = (A *)smem;
   int *ks = (int *)(smem + L.max_rows);
   for (int i = threadIdx.x; i < m; i += kAdjThreads) {
-    const double p = pnew[L.rows[r0 + i]];
+    const double p = ub[r0 + i];
     us[i] = (A)((flags & F_DIV_BETA) ? (bn > 0.0 ? p / bn : 0.0) : p);
   }
   if (KEPT)
@@ -233,8 +237,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const T *
       a2 += (A)widen(c2[i]) * u0;
       a3 += (A)widen(c3[i]) * u0;
     }
-    const double z[4] = {wave_sum((double)(a0 + b0)), wave_sum((double)(a1 + b1)),
-                         wave_sum((double)(a2 + b2)), wave_sum((double)(a3 + b3))};
+    const double z[4] = {wave_sum_dpp((double)(a0 + b0)), wave_sum_dpp((double)(a1 + b1)),
+                         wave_sum_dpp((double)(a2 + b2)), wave_sum_dpp((double)(a3 + b3))};
     if (lane < 4 && k + lane < k1) {
       double zz = z[0];
       if (lane == 1) zz = z[1];
@@ -551,7 +555,7 @@ __global__ __launch_bounds__(kVecThreads) void sq_partials(int64_t n, const doub
 }
 
 struct Work {
-  double *t, *p[2], *res, *q[2], *w, *z, *xs, *zs, *dy, *part, *part2;
+  double *t, *ub, *p[2], *res, *q[2], *w, *z, *xs, *zs, *dy, *part, *part2;
   State *st, *st2;
   int64_t npart;
 };
@@ -587,6 +591,7 @@ size_t carve(const rfm_layout *L, char *base, Work *W) {
   };
   Work w{};
   w.t = (double *)take(sizeof(double) * (size_t)L->nnz_rows);
+  w.ub = (double *)take(sizeof(double) * (size_t)L->nnz_rows);
   w.p[0] = (double *)take(sizeof(double) * N);
   w.p[1] = (double *)take(sizeof(double) * N);
   w.res = (double *)take(sizeof(double) * N);
@@ -650,11 +655,14 @@ struct Launcher {
     }
   }
   void gather(hipStream_t s, const double *pcur, double *pnew, State *st, int mode) {
-    hipLaunchKernelGGL(fwd_gather, dim3(g_rows()), dim3(kVecThreads), 0, s, *L, W.t, h, pcur, pnew,
+    hipLaunchKernelGGL(fwd_gather, dim3(g_rows()), dim3(kVecThreads), 0, s, *L, W.t, h, pcur, pnew, W.ub,
                        W.part, W.part2, st, mode);
   }
-  // q = A^T u (- beta v in ITER mode), u = p / beta outside RESID mode; partials of ||q||^2
+  // q = A^T u (- beta v in ITER mode), u = p / beta outside RESID mode; partials of ||q||^2.
+  // p is the vector of the last gather (read from its block-row copy W.ub).
   void adj(hipStream_t s, const double *pnew, const double *qcur, double *qnew, State *st, int mode) {
+    (void)pnew;
+    const double *ubk = W.ub;
     int flags = 0;
     if (mode == ITER) flags = F_CHECK_DONE | F_DIV_BETA | F_COMBINE;
     if (mode == INIT) flags = F_DIV_BETA;
@@ -662,16 +670,16 @@ struct Launcher {
     const int32_t *nk = nullptr;
     if (!rform && dtype == RFM_F32) {
       hipLaunchKernelGGL((adj_local<float, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
-                         (const float *)Qlow, nk, A->rank, pnew, qcur, qnew, W.part, ct, st, flags);
+                         (const float *)Qlow, nk, A->rank, ubk, qcur, qnew, W.part, ct, st, flags);
     } else if (!rform && dtype == RFM_BF16) {
       hipLaunchKernelGGL((adj_local<bf16_t, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
-                         (const bf16_t *)Qlow, nk, A->rank, pnew, qcur, qnew, W.part, ct, st, flags);
+                         (const bf16_t *)Qlow, nk, A->rank, ubk, qcur, qnew, W.part, ct, st, flags);
     } else if (!rform) {
       hipLaunchKernelGGL((adj_local<double, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->Q,
-                         nk, A->rank, pnew, qcur, qnew, W.part, ct, st, flags);
+                         nk, A->rank, ubk, qcur, qnew, W.part, ct, st, flags);
     } else {
       hipLaunchKernelGGL((adj_local<double, true>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->M, A->kept,
-                         A->rank, pnew, qcur, W.zs, W.part, ct, st, flags & ~F_COMBINE);
+                         A->rank, ubk, qcur, W.zs, W.part, ct, st, flags & ~F_COMBINE);
       hipLaunchKernelGGL(trsv_upper_t, dim3(L->J), dim3(kTriThreads), tri_lds(), s, *L, A->rank, A->R, W.zs,
                          qcur, qnew, W.part, st, flags & (F_CHECK_DONE | F_COMBINE));
     }
