@@ -143,6 +143,39 @@ __device__ __forceinline__ void apply_refl_lds(double (&x)[G][TT], const double 
   }
 }
 
+// Sum over each group of 16 lanes (a DPP row) by a rotate butterfly: every lane of the row
+// receives the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_row<0x128>(v);  // row_ror:8
+  v += dpp_row<0x124>(v);  // row_ror:4
+  v += dpp_row<0x122>(v);  // row_ror:2
+  v += dpp_row<0x121>(v);  // row_ror:1
+  return v;
+}
+
+
+// One column per group of 16 lanes (lane i of group g holds rows r0 + i + 16 t, t < R16):
+// x <- H x for the reflector v at V (rows relative to r0, zero-padded to 16 R16) with scalar
+// th; a 16-lane reduction per reflector serves the four columns of a wave at once.
+template <int R16>
+__device__ __forceinline__ void apply_refl16(double (&x)[R16], const double *v, double th) {
+  const int li = threadIdx.x & 15;
+  double f = 0.0;
+#pragma unroll
+  for (int t = 0; t < R16; ++t) f = fma(v[li + 16 * t], x[t], f);
+  f = row16_sum(f);
+  const double g = -th * f;
+#pragma unroll
+  for (int t = 0; t < R16; ++t) x[t] = fma(g, v[li + 16 * t], x[t]);
+}
+
 // ---------------------------------------------------------------- unpivoted QR of the block
 // Reflector i of the current panel: Vp[i * ldv + (row - p)] for rows p..m-1 (zero above its
 // pivot row, 1 on it).  taus: [max_cols] in LDS.
@@ -159,7 +192,8 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
     const double *__restrict__ Mj = M + B.base;
     double *taus = lds;
     double *Vp = lds + L.max_cols;
-    const int ldv = m;
+    constexpr bool Q16 = T <= 12;     // trailing update with one column per 16 lanes
+    const int ldv = Q16 ? 64 * T : m;  // reflector rows zero-padded to 64 T in that case
     for (int64_t e = tid; e < (int64_t)m * n; e += NT) A[e] = Mj[e];
     __syncthreads();
     for (int p = 0; p < nr; p += nb) {
@@ -180,6 +214,7 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
         if (w == i % NW) {
           double *vrow = Vp + (int64_t)i * ldv;
           for (int rr = lane; rr < i; rr += kWave) vrow[rr] = 0.0;
+          for (int rr = m - p + lane; rr < ldv; rr += kWave) vrow[rr] = 0.0;
           double th;
           if (NPC == 1 || i < NW) th = reflect<T>(pc[0], p, s, m, vrow + i);
           else th = reflect<T>(pc[NPC - 1], p, s, m, vrow + i);
@@ -213,6 +248,27 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
         }
       }
       // trailing columns: loaded once, the panel's reflectors in order, stored once
+      if constexpr (Q16) {
+        constexpr int R16 = 4 * T;
+        const int li = lane & 15, qd = lane >> 4;
+        for (int c0 = p + b + 4 * w; c0 < n; c0 += 4 * NW) {
+          const int k = c0 + qd;
+          double x[R16];
+#pragma unroll
+          for (int t = 0; t < R16; ++t) {
+            const int row = p + li + 16 * t;
+            x[t] = (k < n && row < m) ? A[(int64_t)k * m + row] : 0.0;
+          }
+          for (int i = 0; i < b; ++i) apply_refl16<R16>(x, Vp + (int64_t)i * ldv, taus[p + i]);
+          if (k < n) {
+#pragma unroll
+            for (int t = 0; t < R16; ++t) {
+              const int row = p + li + 16 * t;
+              if (row < m) A[(int64_t)k * m + row] = x[t];
+            }
+          }
+        }
+      } else
       for (int c0 = p + b + w * G; c0 < n; c0 += NW * G) {
         double x[G][T];
 #pragma unroll
@@ -277,23 +333,6 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
 __host__ __device__ constexpr size_t qrcp_small_bytes(int nmax, int nreg, int r16) {
   return (size_t)(2 * nmax + (nmax + nreg) + 3 * 16 * r16 + 32) * sizeof(double) +
          (size_t)(2 * (nmax + nreg) + 2 * nmax + 64 + NW + 2) * sizeof(int) + 8;
-}
-
-// Sum over each group of 16 lanes (a DPP row) by a rotate butterfly: every lane of the row
-// receives the same value.
-template <int CTRL>
-__device__ __forceinline__ double dpp_row(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_row<0x128>(v);  // row_ror:8
-  v += dpp_row<0x124>(v);  // row_ror:4
-  v += dpp_row<0x122>(v);  // row_ror:2
-  v += dpp_row<0x121>(v);  // row_ror:1
-  return v;
 }
 
 template <int R16, int S4>
@@ -646,73 +685,60 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
 // ---------------------------------------------------------------- Q1 = H'_0..H'_{r-1} [I_r; 0]
 // Backward over panels of nb reflectors (read from below the diagonal of the R slot, which
 // is cleared as it is consumed); the result Z (nr x r, ld nr) in the block's slot W2.
-template <int TR, int G>
+template <int R16>
 __global__ __launch_bounds__(NT) void rf_formq1(rfm_layout L, const int32_t *__restrict__ rank,
                                                 double *__restrict__ Rout, const double *__restrict__ tau1,
                                                 double *__restrict__ W2, int nb,
                                                 const int32_t *__restrict__ order) {
   extern __shared__ double lds[];
+  constexpr int LD = 16 * R16;  // reflector rows, zero-padded
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  {
-    const int j = order ? order[blockIdx.x] : blockIdx.x;
-    const Blk B = blk(L, j);
-    const int n = B.n, nr = B.nr, r = rank[j];
-    if (r == 0) return;
-    double *__restrict__ R = Rout + B.rsq;
-    double *__restrict__ Z = W2 + B.rsq;
-    double *tl = lds;       // [nb]
-    double *Vp = lds + 16;  // [nb][nr]
-    for (int p = ((r - 1) / nb) * nb; p >= 0; p -= nb) {
-      const int b = min(nb, r - p);
-      for (int e = tid; e < b * (nr - p); e += NT) {
-        const int i = e / (nr - p), rr = e % (nr - p);
-        const int q = p + i, row = p + rr;
-        Vp[i * nr + rr] = (rr < i) ? 0.0 : (rr == i) ? 1.0 : R[(int64_t)q * n + row];
-      }
-      for (int i = tid; i < b; i += NT) tl[i] = tau1[B.f0 + p + i];
-      __syncthreads();
-      for (int e = tid; e < b * (nr - p); e += NT) {
-        const int i = e / (nr - p), rr = e % (nr - p);
-        if (rr > i) R[(int64_t)(p + i) * n + p + rr] = 0.0;
-      }
-      for (int c0 = p + w * G; c0 < r; c0 += NW * G) {
-        double x[G][TR];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const int k = c0 + g;
-#pragma unroll
-          for (int t = 0; t < TR; ++t) {
-            const int row = p + lane + kWave * t;
-            double v = 0.0;
-            if (k < r && row < nr) v = (k < p + b) ? (row == k ? 1.0 : 0.0) : Z[(int64_t)k * nr + row];
-            x[g][t] = v;
-          }
-        }
-        for (int i = b - 1; i >= 0; --i) {
-          double vr[TR];
-#pragma unroll
-          for (int t = 0; t < TR; ++t) {
-            const int rr = lane + kWave * t;
-            vr[t] = (p + rr < nr) ? Vp[i * nr + rr] : 0.0;
-          }
-          apply_refl<TR, G>(x, vr, tl[i]);
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const int k = c0 + g;
-          if (k < r) {
-#pragma unroll
-            for (int t = 0; t < TR; ++t) {
-              const int row = p + lane + kWave * t;
-              if (row < nr) Z[(int64_t)k * nr + row] = x[g][t];
-            }
-            if (k < p + b)
-              for (int row = lane; row < p; row += kWave) Z[(int64_t)k * nr + row] = 0.0;
-          }
-        }
-      }
-      __syncthreads();
+  const int li = lane & 15, qd = lane >> 4;
+  const int j = order ? order[blockIdx.x] : blockIdx.x;
+  const Blk B = blk(L, j);
+  const int n = B.n, nr = B.nr, r = rank[j];
+  if (r == 0) return;
+  double *__restrict__ R = Rout + B.rsq;
+  double *__restrict__ Z = W2 + B.rsq;
+  double *tl = lds;       // [nb]
+  double *Vp = lds + 16;  // [nb][LD]
+  for (int p = ((r - 1) / nb) * nb; p >= 0; p -= nb) {
+    const int b = min(nb, r - p);
+    for (int e = tid; e < b * LD; e += NT) {
+      const int i = e / LD, rr = e % LD;
+      const int q = p + i, row = p + rr;
+      Vp[e] = (row >= nr || rr < i) ? 0.0 : (rr == i) ? 1.0 : R[(int64_t)q * n + row];
     }
+    for (int i = tid; i < b; i += NT) tl[i] = tau1[B.f0 + p + i];
+    __syncthreads();
+    for (int e = tid; e < b * (nr - p); e += NT) {
+      const int i = e / (nr - p), rr = e % (nr - p);
+      if (rr > i) R[(int64_t)(p + i) * n + p + rr] = 0.0;
+    }
+    // one column per group of 16 lanes: columns >= p + b are already formed, the panel's
+    // own columns start as unit vectors
+    for (int c0 = p + 4 * w; c0 < r; c0 += 4 * NW) {
+      const int k = c0 + qd;
+      double x[R16];
+#pragma unroll
+      for (int t = 0; t < R16; ++t) {
+        const int row = p + li + 16 * t;
+        double v = 0.0;
+        if (k < r && row < nr) v = (k < p + b) ? (row == k ? 1.0 : 0.0) : Z[(int64_t)k * nr + row];
+        x[t] = v;
+      }
+      for (int i = b - 1; i >= 0; --i) apply_refl16<R16>(x, Vp + i * LD, tl[i]);
+      if (k < r) {
+#pragma unroll
+        for (int t = 0; t < R16; ++t) {
+          const int row = p + li + 16 * t;
+          if (row < nr) Z[(int64_t)k * nr + row] = x[t];
+        }
+        if (k < p + b)
+          for (int row = li; row < p; row += 16) Z[(int64_t)k * nr + row] = 0.0;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -732,16 +758,43 @@ __global__ __launch_bounds__(NT) void rf_formq0(rfm_layout L, const int32_t *__r
     if (rank[j] == 0) return;
     double *__restrict__ A = Q + B.base;
     double *tl = lds;       // [nb]
-    double *Vp = lds + 16;  // [nb][m]
+    double *Vp = lds + 16;  // [nb][ldv]
+    constexpr bool Q16 = T <= 12;     // one column per 16 lanes
+    const int ldv = Q16 ? 64 * T : m;  // reflector rows zero-padded to 64 T in that case
     for (int p = ((nr - 1) / nb) * nb; p >= 0; p -= nb) {
       const int b = min(nb, nr - p);
-      for (int e = tid; e < b * (m - p); e += NT) {
-        const int i = e / (m - p), rr = e % (m - p);
+      for (int e = tid; e < b * ldv; e += NT) {
+        const int i = e / ldv, rr = e % ldv;
         const int k = p + i, row = p + rr;
-        Vp[(int64_t)i * m + rr] = (rr < i) ? 0.0 : (rr == i) ? 1.0 : A[(int64_t)k * m + row];
+        Vp[e] = (row >= m || rr < i) ? 0.0 : (rr == i) ? 1.0 : A[(int64_t)k * m + row];
       }
       for (int i = tid; i < b; i += NT) tl[i] = tau0[B.f0 + p + i];
       __syncthreads();
+      if constexpr (Q16) {
+        constexpr int R16 = 4 * T;
+        const int li = lane & 15, qd = lane >> 4;
+        for (int c0 = p + 4 * w; c0 < nr; c0 += 4 * NW) {
+          const int k = c0 + qd;
+          double x[R16];
+#pragma unroll
+          for (int t = 0; t < R16; ++t) {
+            const int row = p + li + 16 * t;
+            double v = 0.0;
+            if (k < nr && row < m) v = (k < p + b) ? (row == k ? 1.0 : 0.0) : A[(int64_t)k * m + row];
+            x[t] = v;
+          }
+          for (int i = b - 1; i >= 0; --i) apply_refl16<R16>(x, Vp + (int64_t)i * ldv, tl[i]);
+          if (k < nr) {
+#pragma unroll
+            for (int t = 0; t < R16; ++t) {
+              const int row = p + li + 16 * t;
+              if (row < m) A[(int64_t)k * m + row] = x[t];
+            }
+            if (k < p + b)
+              for (int row = li; row < p; row += 16) A[(int64_t)k * m + row] = 0.0;
+          }
+        }
+      } else
       for (int c0 = p + w * G; c0 < nr; c0 += NW * G) {
         double x[G][T];
 #pragma unroll
@@ -757,13 +810,13 @@ __global__ __launch_bounds__(NT) void rf_formq0(rfm_layout L, const int32_t *__r
         }
         for (int i = b - 1; i >= 0; --i) {
           if constexpr (T >= 24) {
-            apply_refl_lds<T, G>(x, Vp + (int64_t)i * m, m - p, tl[i]);
+            apply_refl_lds<T, G>(x, Vp + (int64_t)i * ldv, m - p, tl[i]);
           } else {
             double vr[T];
 #pragma unroll
             for (int t = 0; t < T; ++t) {
               const int rr = lane + kWave * t;
-              vr[t] = (p + rr < m) ? Vp[(int64_t)i * m + rr] : 0.0;
+              vr[t] = (p + rr < m) ? Vp[(int64_t)i * ldv + rr] : 0.0;
             }
             apply_refl<T, G>(x, vr, tl[i]);
           }
@@ -912,18 +965,24 @@ rfm_status prep(K kern, size_t lds) {
 }
 
 template <int T>
-rfm_status launch_tall(const RfirstArgs &a, const Ws &W, int nb, bool first) {
+rfm_status launch_tall(const RfirstArgs &a, const Ws &W, bool first) {
   const rfm_layout *L = a.L;
   constexpr int GG = g_of(T);
   const dim3 grid((unsigned)L->J);
+  // reflector rows in LDS: zero-padded to 64 T for the 16-lane layout (T <= 12), else
+  // max_rows; panel width nb from the LDS budget, at most the panel columns the waves hold in
+  // registers
+  const size_t ldv = (T <= 12) ? (size_t)64 * T : (size_t)std::max(1, L->max_rows);
+  int nb = (int)((140 * 1024 - (size_t)L->max_cols * sizeof(double)) / (ldv * sizeof(double)));
+  nb = std::max(1, std::min(npc_of(T) * NW, nb));
   if (first) {
-    const size_t lds = ((size_t)L->max_cols + (size_t)nb * L->max_rows) * sizeof(double);
+    const size_t lds = ((size_t)L->max_cols + (size_t)nb * ldv) * sizeof(double);
     auto kern = rf_qr<T, GG, npc_of(T)>;
     rfm_status s = prep(kern, lds);
     if (s != RFM_OK) return s;
     hipLaunchKernelGGL(kern, grid, dim3(NT), lds, a.st, *L, a.M, a.Q, W.tau0, nb, a.order);
   } else {
-    const size_t lds = (16 + (size_t)nb * L->max_rows) * sizeof(double);
+    const size_t lds = (16 + (size_t)nb * ldv) * sizeof(double);
     auto kern = rf_formq0<T, GG>;
     rfm_status s = prep(kern, lds);
     if (s != RFM_OK) return s;
@@ -933,20 +992,20 @@ rfm_status launch_tall(const RfirstArgs &a, const Ws &W, int nb, bool first) {
   return RFM_OK;
 }
 
-rfm_status dispatch_tall(const RfirstArgs &a, const Ws &W, int nb, bool first) {
+rfm_status dispatch_tall(const RfirstArgs &a, const Ws &W, bool first) {
   const int mr = a.L->max_rows;
-  if (mr <= 64) return launch_tall<1>(a, W, nb, first);
-  if (mr <= 128) return launch_tall<2>(a, W, nb, first);
-  if (mr <= 256) return launch_tall<4>(a, W, nb, first);
-  if (mr <= 512) return launch_tall<8>(a, W, nb, first);
-  if (mr <= 768) return launch_tall<12>(a, W, nb, first);
-  if (mr <= 1024) return launch_tall<16>(a, W, nb, first);
-  if (mr <= 1536) return launch_tall<24>(a, W, nb, first);
-  if (mr <= 2048) return launch_tall<32>(a, W, nb, first);
-  return launch_tall<48>(a, W, nb, first);
+  if (mr <= 64) return launch_tall<1>(a, W, first);
+  if (mr <= 128) return launch_tall<2>(a, W, first);
+  if (mr <= 256) return launch_tall<4>(a, W, first);
+  if (mr <= 512) return launch_tall<8>(a, W, first);
+  if (mr <= 768) return launch_tall<12>(a, W, first);
+  if (mr <= 1024) return launch_tall<16>(a, W, first);
+  if (mr <= 1536) return launch_tall<24>(a, W, first);
+  if (mr <= 2048) return launch_tall<32>(a, W, first);
+  return launch_tall<48>(a, W, first);
 }
 
-template <int R16, int S4, int GQ1>
+template <int R16, int S4>
 rfm_status launch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
   constexpr int TR = R16 / 4;
   const rfm_layout *L = a.L;
@@ -969,8 +1028,8 @@ rfm_status launch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
   }
   {
     const int nb = 16;
-    const size_t lds1 = (16 + (size_t)nb * nr_max) * sizeof(double);
-    auto kern = rf_formq1<TR, GQ1>;
+    const size_t lds1 = (16 + (size_t)nb * 16 * R16) * sizeof(double);
+    auto kern = rf_formq1<R16>;
     rfm_status s = prep(kern, lds1);
     if (s != RFM_OK) return s;
     hipLaunchKernelGGL(kern, grid, dim3(NT), lds1, a.st, *L, a.rank, a.R, W.tau1, W.W2, nb, a.order);
@@ -981,11 +1040,11 @@ rfm_status launch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
 
 rfm_status dispatch_small(const RfirstArgs &a, const Ws &W, int nr_max) {
   switch (r16_of(nr_max)) {
-    case 4: return launch_small<4, 8, 8>(a, W, nr_max);
-    case 8: return launch_small<8, 8, 8>(a, W, nr_max);
-    case 16: return launch_small<16, 4, 4>(a, W, nr_max);
-    case 20: return launch_small<20, 3, 4>(a, W, nr_max);
-    default: return launch_small<32, 1, 2>(a, W, nr_max);
+    case 4: return launch_small<4, 8>(a, W, nr_max);
+    case 8: return launch_small<8, 8>(a, W, nr_max);
+    case 16: return launch_small<16, 4>(a, W, nr_max);
+    case 20: return launch_small<20, 3>(a, W, nr_max);
+    default: return launch_small<32, 1>(a, W, nr_max);
   }
 }
 
@@ -1004,16 +1063,11 @@ rfm_status rrqr_rfirst(const RfirstArgs &a) {
   Ws W;
   carve(L, (char *)a.ws, &W);
   const int nr_max = nr_max_of(L);
-  const int mr = std::max(1, L->max_rows);
-  // panel width of the tall passes: nb reflectors of max_rows entries in LDS, at most the
-  // panel columns the waves hold in registers
-  int nb = (int)((140 * 1024 - (size_t)L->max_cols * sizeof(double)) / ((size_t)mr * sizeof(double)));
-  nb = std::max(1, std::min(mr > 1024 ? NW : 2 * NW, nb));
-  rfm_status s = dispatch_tall(a, W, nb, true);
+  rfm_status s = dispatch_tall(a, W, true);
   if (s != RFM_OK) return s;
   s = dispatch_small(a, W, nr_max);
   if (s != RFM_OK) return s;
-  s = dispatch_tall(a, W, nb, false);
+  s = dispatch_tall(a, W, false);
   if (s != RFM_OK) return s;
   const dim3 grid((unsigned)L->J);
   if (nr_max <= 256)
