@@ -841,34 +841,40 @@ __global__ __launch_bounds__(NT) void rf_formq0(rfm_layout L, const int32_t *__r
 }
 
 // ---------------------------------------------------------------- Q_hat = Q0 Q1 D in place
-// Row tiles of RT = 16384 / CP rows; every thread accumulates a 4 x 8 tile of the RT x CP
-// output (CP >= r) over slices of 16 of the nr inner indices staged in LDS (Q0 rows
-// As[k][row], Q1 rows Zs[k][q]).  The tile is written (times the sign normalisation) only
-// after its last slice, so the rows it overwrites have been read.
+// Row tiles of RT = 16384 / CP rows of the RT x CP output (CP >= r), computed with FP64
+// matrix cores: each wave owns 2 x 4 tiles of 16 x 16 and accumulates them with
+// v_mfma_f64_16x16x4f64 over slices of 16 of the nr inner indices staged in LDS (Q0 rows
+// As[k][row], Q1 rows Zs[k][q]; the next slice's loads are in flight while one is
+// multiplied).  Operand layout of the instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] of a 16x4 by 4x16 product and holds D[l / 16 + 4 v][l % 16] in element v
+// of its accumulator.  The tile is written (times the sign normalisation) only after its last
+// slice, so the rows it overwrites have been read.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
 template <int CP>
 __global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__restrict__ rank,
                                               double *__restrict__ Q, const double *__restrict__ W2,
                                               const double *__restrict__ dsgn, const int32_t *__restrict__ order) {
-  constexpr int RT = 16384 / CP, KC = 16, NC = CP / 8;
+  constexpr int RT = 16384 / CP, KC = 16;
+  constexpr int RT16 = RT / 16, WR = RT16 / 2;  // row-tile pairs; waves laid out WR x (NW / WR)
   __shared__ double As[KC][RT];
   __shared__ double Zs[KC][CP];
-  const int tid = threadIdx.x;
-  const int tc = tid % NC, tr = tid / NC;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int wr = w % WR, wc = w / WR;
+  const int li = lane & 15, lk = lane >> 4;
   const int j = order ? order[blockIdx.x] : blockIdx.x;
   const Blk B = blk(L, j);
   const int m = B.m, nr = B.nr, r = rank[j];
   if (r == 0) return;
   double *__restrict__ A = Q + B.base;
   const double *__restrict__ Z = W2 + B.rsq;
+  constexpr int NA = KC * RT / NT, NZ = KC * CP / NT;
   for (int i0 = 0; i0 < m; i0 += RT) {
-    double acc[4][8];
+    d4_t acc[2][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
-    // slices staged through registers: the loads of slice k0 + KC are in flight while
-    // slice k0 is multiplied
-    constexpr int NA = KC * RT / NT, NZ = KC * CP / NT;
+      for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
     double pa[NA], pz[NZ];
     auto fetch = [&](int k0) {
 #pragma unroll
@@ -896,30 +902,32 @@ __global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__res
       }
       __syncthreads();
       if (k0 + KC < nr) fetch(k0 + KC);
-#pragma unroll 4
-      for (int kk = 0; kk < KC; ++kk) {
-        double av[4], zv[8];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) av[a] = As[kk][4 * tr + a];
+      for (int kq = 0; kq < KC; kq += 4) {
+        double av[2], bv[4];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) zv[b] = Zs[kk][8 * tc + b];
+        for (int a = 0; a < 2; ++a) av[a] = As[kq + lk][(2 * wr + a) * 16 + li];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) bv[b] = Zs[kq + lk][(4 * wc + b) * 16 + li];
 #pragma unroll
-          for (int b = 0; b < 8; ++b) acc[a][b] += av[a] * zv[b];
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
       __syncthreads();
     }
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int q = 8 * tc + b;
+    for (int b = 0; b < 4; ++b) {
+      const int q = (4 * wc + b) * 16 + li;
       if (q < r) {
         const double sg = dsgn[B.f0 + q];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int row = i0 + 4 * tr + a;
-          if (row < m) A[(int64_t)q * m + row] = sg * acc[a][b];
-        }
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = i0 + (2 * wr + a) * 16 + lk + 4 * v;
+            if (row < m) A[(int64_t)q * m + row] = sg * acc[a][b][v];
+          }
       }
     }
   }
