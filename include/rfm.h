@@ -126,6 +126,17 @@ size_t rfm_assemble_ws_bytes(const rfm_layout *L);
 rfm_status rfm_assemble(const rfm_layout *L, const rfm_problem *P, double *M, double *h,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* Precision form of the assembly: the entries of rfm_assemble evaluated in binary32
+ * arithmetic (inputs rounded to binary32 once; windows, features and operator in binary32)
+ * and stored as binary32 (dtype RFM_F32) or as bfloat16 (RFM_BF16: round to nearest even
+ * of the binary32 value, stored as its upper 16 bits).  M device [nnz] of that type in the
+ * block layout; h device [N] in binary64 as in rfm_assemble; ws as rfm_assemble.  The
+ * entries are not accurate enough for the filter at small tau (their error against the
+ * binary64 entries is measured by the tests); they are an input for studies of the
+ * precision form. */
+rfm_status rfm_assemble_low(const rfm_layout *L, const rfm_problem *P, int32_t dtype, void *M,
+                            double *h, void *ws, size_t ws_bytes, void *stream);
+
 /* Bytes of device workspace rfm_rrqr_filter needs for this layout. */
 size_t rfm_rrqr_ws_bytes(const rfm_layout *L);
 
@@ -311,6 +322,21 @@ rfm_status rfm_lsqr_multi(const rfm_layout *L, const rfm_operator *A, const doub
  * feat_off[j] + k, local feature order). */
 rfm_status rfm_coefficients(const rfm_layout *L, const int32_t *rank, const int32_t *kept,
                             const double *R, const double *y, double *a, void *stream);
+
+/* Bytes of device workspace rfm_evaluate needs for a test-point layout. */
+size_t rfm_evaluate_ws_bytes(const rfm_layout *L);
+
+/* Solution at test points and its error (Sec. 4.2 performance evaluation; eq. elm_solution
+ * with the windows of eq. used_window_function_nd): u_hat(x_t) = sum over the subdomains j
+ * covering x_t (strict |x - mu| < hw) of w_j(x_t) sum_k a_(j,k) tanh(w_(j,k) . (x_t - mu_j)/hw_j
+ * + b_(j,k)), and, with u_exact, e_L1 = mean_t |u_hat - u| / std(u) (population standard
+ * deviation over the test points).  Lt: a layout planned (rfm_plan) on the test points with
+ * the same subdomains and feature counts; P: its x = test points [T*d] (device), mu, hw, w, b
+ * as for the assembly (the other fields are not read).  a device [ncols] (rfm_coefficients);
+ * uhat device [T]; u_exact device [T] and e_l1 host [1], both nullable together.  Sync when
+ * e_l1 is requested.  ws: rfm_evaluate_ws_bytes(Lt). */
+rfm_status rfm_evaluate(const rfm_layout *Lt, const rfm_problem *P, const double *a, double *uhat,
+                        const double *u_exact, double *e_l1, void *ws, size_t ws_bytes, void *stream);
 
 /* Learned warm start (the form that maps the parameters of a PDE family to LSQR starting
  * coordinates): a 3-layer perceptron n_in -> n_hidden -> n_hidden -> n_out with tanh hidden

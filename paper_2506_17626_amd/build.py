@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "librfm.so")
 
-SOURCES = ["plan.cpp", "tune.cpp", "assemble.hip", "rrqr.hip", "rrqr_rfirst.hip", "lsqr.hip", "mrhs.hip", "mlp.hip", "learned.hip"]
+SOURCES = ["plan.cpp", "tune.cpp", "assemble.hip", "rrqr.hip", "rrqr_rfirst.hip", "lsqr.hip", "mrhs.hip", "mlp.hip", "learned.hip", "evaluate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

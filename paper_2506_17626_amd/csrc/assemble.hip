@@ -9,6 +9,8 @@
 //   with coalesced 64-wide stores; each thread produces a run of features for its row,
 //   reusing the row's point and window data.  Entry = s_r Op_r[w_j phi_jk](x_r) by the
 //   product rule with phi = tanh(w . xn + b), xn = (x - mu_j)/hw_j (eq. fcn_depth_h).
+// Both run in binary64, or in binary32 for the precision form (rfm_assemble_low), whose
+// entries are stored as binary32 or bfloat16.
 #include "common.hpp"
 
 namespace rfm {
@@ -17,28 +19,31 @@ namespace {
 constexpr int kRowsPerBlock = 256;
 constexpr int kFeatPerThread = 32;
 
-template <int D>
-__device__ __forceinline__ void window_factors(const double *xr, const double *mu,
-                                               const double *hw, double &W, double *dW,
-                                               double *ddW) {
-  const double pi = 3.141592653589793;
-  double f[D], f1[D], f2[D];
+// Tc: the arithmetic (double, or float for the precision form); inputs are read as double
+// and rounded to Tc once.
+template <int D, typename Tc>
+__device__ __forceinline__ void window_factors(const Tc *xr, const double *mu,
+                                               const double *hw, Tc &W, Tc *dW,
+                                               Tc *ddW) {
+  const Tc pi = (Tc)3.141592653589793;
+  Tc f[D], f1[D], f2[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    const double t = (xr[i] - mu[i]) / hw[i];
-    const double cs = cos(pi * t);
-    const double c = 1.0 + cs;
-    const double s = sin(pi * t);
+    const Tc h = (Tc)hw[i];
+    const Tc t = (xr[i] - (Tc)mu[i]) / h;
+    const Tc cs = cos(pi * t);
+    const Tc c = (Tc)1 + cs;
+    const Tc s = sin(pi * t);
     f[i] = c * c;
-    f1[i] = -(2.0 * pi / hw[i]) * s * c;
-    f2[i] = (2.0 * pi * pi / (hw[i] * hw[i])) * (s * s - cs * c);
+    f1[i] = -((Tc)2 * pi / h) * s * c;
+    f2[i] = ((Tc)2 * pi * pi / (h * h)) * (s * s - cs * c);
   }
-  W = 1.0;
+  W = (Tc)1;
 #pragma unroll
   for (int i = 0; i < D; ++i) W *= f[i];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    double others = 1.0;
+    Tc others = (Tc)1;
 #pragma unroll
     for (int l = 0; l < D; ++l)
       if (l != i) others *= f[l];
@@ -47,24 +52,24 @@ __device__ __forceinline__ void window_factors(const double *xr, const double *m
   }
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void window_table(rfm_layout L, rfm_problem P, double *win,
+template <int D, typename Tc>
+__global__ __launch_bounds__(256) void window_table(rfm_layout L, rfm_problem P, Tc *win,
                                                     double *h) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= L.N) return;
   h[r] = P.weight[r] * P.rhs[r];
-  double xr[D];
+  Tc xr[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) xr[i] = P.x[r * D + i];
-  double S = 0.0, dS[D], ddS[D];
+  for (int i = 0; i < D; ++i) xr[i] = (Tc)P.x[r * D + i];
+  Tc S = 0, dS[D], ddS[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) dS[i] = ddS[i] = 0.0;
+  for (int i = 0; i < D; ++i) dS[i] = ddS[i] = 0;
   const int64_t q0 = L.rinc_off[r], q1 = L.rinc_off[r + 1];
   for (int64_t q = q0; q < q1; ++q) {
     const int64_t p = L.rinc[q];
     const int32_t j = L.inc_blk[p];
-    double W, dW[D], ddW[D];
-    window_factors<D>(xr, P.mu + (int64_t)j * D, P.hw + (int64_t)j * D, W, dW, ddW);
+    Tc W, dW[D], ddW[D];
+    window_factors<D, Tc>(xr, P.mu + (int64_t)j * D, P.hw + (int64_t)j * D, W, dW, ddW);
     S += W;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -75,23 +80,36 @@ __global__ __launch_bounds__(256) void window_table(rfm_layout L, rfm_problem P,
   for (int64_t q = q0; q < q1; ++q) {
     const int64_t p = L.rinc[q];
     const int32_t j = L.inc_blk[p];
-    double W, dW[D], ddW[D];
-    window_factors<D>(xr, P.mu + (int64_t)j * D, P.hw + (int64_t)j * D, W, dW, ddW);
-    const double w = W / S;
-    double *out = win + p * (1 + 2 * D);
+    Tc W, dW[D], ddW[D];
+    window_factors<D, Tc>(xr, P.mu + (int64_t)j * D, P.hw + (int64_t)j * D, W, dW, ddW);
+    const Tc w = W / S;
+    Tc *out = win + p * (1 + 2 * D);
     out[0] = w;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      const double dw = (dW[i] - w * dS[i]) / S;
+      const Tc dw = (dW[i] - w * dS[i]) / S;
       out[1 + i] = dw;
-      out[1 + D + i] = (ddW[i] - 2.0 * dw * dS[i] - w * ddS[i]) / S;
+      out[1 + D + i] = (ddW[i] - (Tc)2 * dw * dS[i] - w * ddS[i]) / S;
     }
   }
 }
 
-template <int D>
+// Output element: binary64, binary32, or bfloat16 (round to nearest even on the binary32
+// value, kept as its upper 16 bits).
+template <typename To> struct Out;
+template <> struct Out<double> { static __device__ double put(double v) { return v; } };
+template <> struct Out<float> { static __device__ float put(float v) { return v; } };
+template <> struct Out<uint16_t> {
+  static __device__ uint16_t put(float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+  }
+};
+
+template <int D, typename Tc, typename To>
 __global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, rfm_problem P,
-                                                                  const double *win, double *M) {
+                                                                  const Tc *win, To *M) {
   const int j = blockIdx.z;
   const int64_t r0 = L.row_off[j];
   const int m = (int)(L.row_off[j + 1] - r0);
@@ -102,68 +120,89 @@ __global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, 
   if (i >= m || k0 >= K) return;
   const int64_t p = r0 + i;
   const int32_t r = L.rows[p];
-  double xn[D], hwj[D];
+  Tc xn[D], hwj[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const double h = P.hw[(int64_t)j * D + a];
-    xn[a] = (P.x[(int64_t)r * D + a] - P.mu[(int64_t)j * D + a]) / h;
+    const Tc h = (Tc)P.hw[(int64_t)j * D + a];
+    xn[a] = ((Tc)P.x[(int64_t)r * D + a] - (Tc)P.mu[(int64_t)j * D + a]) / h;
     hwj[a] = h;
   }
-  const double *wp = win + p * (1 + 2 * D);
-  const double w = wp[0];
-  double dw[D], ddw[D];
+  const Tc *wp = win + p * (1 + 2 * D);
+  const Tc w = wp[0];
+  Tc dw[D], ddw[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     dw[a] = wp[1 + a];
     ddw[a] = wp[1 + D + a];
   }
   const int op = P.rowop[r];
-  const double sr = P.weight[r];
-  const double kappa = P.kappa, ksq = P.ksq;
-  double *out = M + L.blk_off[j] + (int64_t)i;
+  const Tc sr = (Tc)P.weight[r];
+  const Tc kappa = (Tc)P.kappa, ksq = (Tc)P.ksq;
+  To *out = M + L.blk_off[j] + (int64_t)i;
   const int k1 = min(K, k0 + kFeatPerThread);
   for (int k = k0; k < k1; ++k) {
     const double *wk = P.w + (f0 + k) * D;
-    double s = 0.0;
+    Tc s = 0;
 #pragma unroll
-    for (int a = 0; a < D; ++a) s += xn[a] * wk[a];
-    s += P.b[f0 + k];
-    const double t = tanh(s);
-    const double g = 1.0 - t * t;
-    const double psi = w * t;
-    double lap = 0.0, spatial = 0.0, dlast = 0.0;
+    for (int a = 0; a < D; ++a) s += xn[a] * (Tc)wk[a];
+    s += (Tc)P.b[f0 + k];
+    const Tc t = tanh(s);
+    const Tc g = (Tc)1 - t * t;
+    const Tc psi = w * t;
+    Tc lap = 0, spatial = 0, dlast = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const double sc = wk[a] / hwj[a];
-      const double dphi = g * sc;
-      const double ddphi = (-2.0 * t * g) * (sc * sc);
-      const double dpsi = dw[a] * t + w * dphi;
-      const double ddpsi = ddw[a] * t + 2.0 * dw[a] * dphi + w * ddphi;
+      const Tc sc = (Tc)wk[a] / hwj[a];
+      const Tc dphi = g * sc;
+      const Tc ddphi = ((Tc)-2 * t * g) * (sc * sc);
+      const Tc dpsi = dw[a] * t + w * dphi;
+      const Tc ddpsi = ddw[a] * t + (Tc)2 * dw[a] * dphi + w * ddphi;
       lap += ddpsi;
       if (a < D - 1) spatial += ddpsi;
       if (a == D - 1) dlast = dpsi;
     }
-    double v;
+    Tc v;
     switch (op) {
       case RFM_OP_NEG_LAPLACE: v = -lap; break;
-      case RFM_OP_HEAT: v = dlast - kappa * (D > 1 ? spatial : 0.0); break;
+      case RFM_OP_HEAT: v = dlast - kappa * (D > 1 ? spatial : (Tc)0); break;
       case RFM_OP_HELMHOLTZ: v = lap + ksq * psi; break;
       default: v = psi; break;
     }
-    out[(int64_t)k * m] = sr * v;
+    out[(int64_t)k * m] = Out<To>::put(sr * v);
   }
 }
 
-template <int D>
-rfm_status launch(const rfm_layout *L, const rfm_problem *P, double *M, double *h, double *win,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(window_table<D>, dim3(ceil_div(L->N, 256)), dim3(256), 0, st, *L, *P, win, h);
+template <int D, typename Tc, typename To>
+rfm_status launch(const rfm_layout *L, const rfm_problem *P, To *M, double *h, Tc *win, hipStream_t st) {
+  hipLaunchKernelGGL((window_table<D, Tc>), dim3(ceil_div(L->N, 256)), dim3(256), 0, st, *L, *P, win, h);
   RFM_LAUNCH_CHECK();
   if (L->max_rows > 0 && L->max_cols > 0) {
     dim3 grid(ceil_div(L->max_rows, kRowsPerBlock), ceil_div(L->max_cols, kFeatPerThread), L->J);
-    hipLaunchKernelGGL(assemble_entries<D>, grid, dim3(kRowsPerBlock), 0, st, *L, *P, win, M);
+    hipLaunchKernelGGL((assemble_entries<D, Tc, To>), grid, dim3(kRowsPerBlock), 0, st, *L, *P, win, M);
     RFM_LAUNCH_CHECK();
   }
+  return RFM_OK;
+}
+
+template <typename Tc, typename To>
+rfm_status launch_d(const rfm_layout *L, const rfm_problem *P, To *M, double *h, void *ws, hipStream_t st) {
+  Tc *win = (Tc *)ws;
+  switch (L->d) {
+    case 1: return launch<1, Tc, To>(L, P, M, h, win, st);
+    case 2: return launch<2, Tc, To>(L, P, M, h, win, st);
+    default: return launch<3, Tc, To>(L, P, M, h, win, st);
+  }
+}
+
+rfm_status check_problem(const rfm_layout *L, const rfm_problem *P, const void *M, const double *h,
+                         const void *ws, size_t ws_bytes, const char *who) {
+  rfm_status s = check_layout(L, who);
+  if (s != RFM_OK) return s;
+  if (!P || !P->x || !P->rowop || !P->weight || !P->rhs || !P->mu || !P->hw || !P->w || !P->b)
+    return fail(RFM_EINVAL, std::string(who) + ": null problem array");
+  if (!h || (L->nnz > 0 && !M)) return fail(RFM_EINVAL, std::string(who) + ": null output");
+  if (ws_bytes < rfm_assemble_ws_bytes(L) || (rfm_assemble_ws_bytes(L) > 0 && !ws))
+    return fail(RFM_EINVAL, std::string(who) + ": workspace too small");
   return RFM_OK;
 }
 
@@ -192,18 +231,17 @@ extern "C" size_t rfm_assemble_ws_bytes(const rfm_layout *L) {
 extern "C" rfm_status rfm_assemble(const rfm_layout *L, const rfm_problem *P, double *M, double *h,
                                    void *ws, size_t ws_bytes, void *stream) {
   using namespace rfm;
-  rfm_status s = check_layout(L, "rfm_assemble");
+  rfm_status s = check_problem(L, P, M, h, ws, ws_bytes, "rfm_assemble");
   if (s != RFM_OK) return s;
-  if (!P || !P->x || !P->rowop || !P->weight || !P->rhs || !P->mu || !P->hw || !P->w || !P->b)
-    return fail(RFM_EINVAL, "rfm_assemble: null problem array");
-  if (!h || (L->nnz > 0 && !M)) return fail(RFM_EINVAL, "rfm_assemble: null output");
-  if (ws_bytes < rfm_assemble_ws_bytes(L) || (rfm_assemble_ws_bytes(L) > 0 && !ws))
-    return fail(RFM_EINVAL, "rfm_assemble: workspace too small");
-  hipStream_t st = (hipStream_t)stream;
-  double *win = (double *)ws;
-  switch (L->d) {
-    case 1: return launch<1>(L, P, M, h, win, st);
-    case 2: return launch<2>(L, P, M, h, win, st);
-    default: return launch<3>(L, P, M, h, win, st);
-  }
+  return launch_d<double, double>(L, P, M, h, ws, (hipStream_t)stream);
+}
+
+extern "C" rfm_status rfm_assemble_low(const rfm_layout *L, const rfm_problem *P, int32_t dtype, void *M,
+                                       double *h, void *ws, size_t ws_bytes, void *stream) {
+  using namespace rfm;
+  rfm_status s = check_problem(L, P, M, h, ws, ws_bytes, "rfm_assemble_low");
+  if (s != RFM_OK) return s;
+  if (dtype == RFM_F32) return launch_d<float, float>(L, P, (float *)M, h, ws, (hipStream_t)stream);
+  if (dtype == RFM_BF16) return launch_d<float, uint16_t>(L, P, (uint16_t *)M, h, ws, (hipStream_t)stream);
+  return fail(RFM_EINVAL, "rfm_assemble_low: dtype must be RFM_F32 or RFM_BF16");
 }

@@ -216,6 +216,61 @@ def rfm_assemble(plan: Plan, prob: dict, M=None, h=None):
     return M, h
 
 
+_lib.rfm_assemble_low.restype = C.c_int
+_lib.rfm_assemble_low.argtypes = [C.POINTER(Layout), C.POINTER(Problem), C.c_int32, _p, _p, _p, C.c_size_t, _p]
+EXPORTED += ["rfm_assemble_low"]
+
+
+def rfm_assemble_low(plan: Plan, prob: dict, dtype=F32, M=None, h=None):
+    """Entries evaluated in binary32, stored as float32 (F32) or bfloat16 (BF16)."""
+    L = plan.layout
+    dev = prob["x"].device
+    tdt = {F32: torch.float32, BF16: torch.bfloat16}[dtype]
+    M = torch.empty(max(L.nnz, 1), dtype=tdt, device=dev) if M is None else M
+    h = torch.empty(L.N, dtype=torch.float64, device=dev) if h is None else h
+    P = Problem(x=prob["x"].data_ptr(), rowop=prob["rowop"].data_ptr(), weight=prob["weight"].data_ptr(),
+                rhs=prob["rhs"].data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(),
+                w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"])
+    nb = _lib.rfm_assemble_ws_bytes(C.byref(L))
+    ws = _ws(nb, dev)
+    _check(_lib.rfm_assemble_low(C.byref(L), C.byref(P), int(dtype), _ptr(M), _ptr(h), _ptr(ws), nb, _stream()),
+           "rfm_assemble_low")
+    return M, h
+
+
+_lib.rfm_evaluate_ws_bytes.restype = C.c_size_t
+_lib.rfm_evaluate_ws_bytes.argtypes = [C.POINTER(Layout)]
+_lib.rfm_evaluate.restype = C.c_int
+_lib.rfm_evaluate.argtypes = [C.POINTER(Layout), C.POINTER(Problem), _p, _p, _p, C.POINTER(C.c_double), _p,
+                              C.c_size_t, _p]
+EXPORTED += ["rfm_evaluate_ws_bytes", "rfm_evaluate"]
+
+
+def evaluation_points(inst, xt: np.ndarray, device="cuda"):
+    """Layout of the test points xt [T, d] over the instance's subdomains, and xt on the
+    device (host planning, once per point set)."""
+    tplan = rfm_plan(inst.d, inst.J, xt, inst.mu, inst.hw, np.diff(inst.feat_off), device)
+    xd = torch.from_numpy(np.ascontiguousarray(xt, dtype=np.float64)).to(device)
+    return tplan, xd
+
+
+def rfm_evaluate(tplan: Plan, xd, prob: dict, a, u_exact=None, ws=None):
+    """u_hat at the test points for coefficients a (device [ncols]); with u_exact (device
+    [T]) also e_L1.  Returns (uhat, e_l1 or None)."""
+    L = tplan.layout
+    dev = xd.device
+    P = Problem(x=xd.data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(), w=prob["w"].data_ptr(),
+                b=prob["b"].data_ptr())
+    uhat = torch.empty(L.N, dtype=torch.float64, device=dev)
+    nb = _lib.rfm_evaluate_ws_bytes(C.byref(L))
+    if ws is None or ws.numel() < nb:
+        ws = _ws(nb, dev)
+    e = C.c_double(0.0)
+    _check(_lib.rfm_evaluate(C.byref(L), C.byref(P), _ptr(a), _ptr(uhat), _ptr(u_exact),
+                             C.byref(e) if u_exact is not None else None, _ptr(ws), nb, _stream()), "rfm_evaluate")
+    return uhat, (e.value if u_exact is not None else None)
+
+
 def rfm_plan_order(plan: Plan):
     """Block ids by decreasing factorisation cost (host), copied to the device."""
     order = np.zeros(plan.J, dtype=np.int32)

@@ -553,3 +553,71 @@ def test_multi_rhs_warm_start_guard_per_column(rfm):
         assert iw[b] == ic[b] and torch.equal(Yw[:, b], Yc[:, b])
     for b in (0, 2):
         assert iw[b] <= 2
+
+
+@pytest.mark.parametrize("name", TINY)
+def test_evaluation_and_l1_error_match_oracle(rfm, name):
+    """u_hat at the test grid and e_L1 (Sec. 4.2) from the GPU against the oracle's
+    evaluation of the same coefficients; u_hat within 64 u times the absolute-value
+    evaluation sum_j w_j sum_k |a_jk| |phi_jk| (cancellation between features is the
+    rule for these coefficients)."""
+    inst = I.tiny(name)
+    print(f"[evaluate] {name}", flush=True)
+    rng = np.random.default_rng(21)
+    a = rng.standard_normal(inst.feat_off[-1]) * 10.0 ** rng.uniform(-2, 3, inst.feat_off[-1])
+    xt = inst.test_points(7 if inst.d == 3 else 12 if inst.d == 2 else 40)
+    prob = rfm.problem_tensors(inst)
+    ue = inst.exact(xt)
+    tplan, xd = rfm.evaluation_points(inst, xt)
+    uh, e = rfm.rfm_evaluate(tplan, xd, prob, _dev(a), u_exact=_dev(ue))
+    torch.cuda.synchronize()
+    uo = osolve.evaluate(inst, a, xt)
+    # absolute-value evaluation of the same formula
+    scale = np.zeros(len(xt))
+    rows = [np.nonzero(assembly.support_mask(xt, inst.mu[j], inst.hw[j]))[0] for j in range(inst.J)]
+    S = np.zeros(len(xt))
+    for j in range(inst.J):
+        W, _, _ = assembly.unnormalised_window(xt[rows[j]], inst.mu[j], inst.hw[j])
+        S[rows[j]] += W
+    for j in range(inst.J):
+        r = rows[j]
+        if r.size == 0:
+            continue
+        k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
+        phi, _, _ = assembly.features(xt[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1])
+        W, _, _ = assembly.unnormalised_window(xt[r], inst.mu[j], inst.hw[j])
+        scale[r] += (W / S[r]) * (np.abs(phi) @ np.abs(a[k0:k1]))
+    err = np.abs(uh.cpu().numpy() - uo)
+    assert np.all(err <= 64 * U * scale + 1e-300), float((err / (U * scale + 1e-300)).max())
+    eo = float(np.mean(np.abs(uo - ue)) / np.std(ue))
+    assert abs(e - eo) <= 1e-9 * eo, (e, eo)
+    # without the exact solution only u_hat is produced
+    uh2, e2 = rfm.rfm_evaluate(tplan, xd, prob, _dev(a))
+    assert e2 is None and torch.equal(uh2, uh)
+
+
+@pytest.mark.parametrize("name", TINY)
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_low_precision_assembly_error_against_oracle(rfm, name, dtype):
+    """The precision form's assembly (binary32 arithmetic, binary32 or bfloat16 storage):
+    normwise relative error per block against the binary64 oracle, measured and reported;
+    bounded by 1e-3 (binary32) and 1e-2 (bfloat16: its own rounding is 2^-9 relative)."""
+    inst = I.tiny(name)
+    plan, prob = _setup(rfm, inst)
+    Ml, h = rfm.rfm_assemble_low(plan, prob, rfm.F32 if dtype == "f32" else rfm.BF16)
+    M64, h64 = rfm.rfm_assemble(plan, prob)
+    torch.cuda.synchronize()
+    assert torch.equal(h, h64)
+    rows, blocks, _ = assembly.assemble(inst)
+    Mh = Ml.to(torch.float64).cpu().numpy()
+    K = np.diff(inst.feat_off)
+    rel = []
+    for j in range(inst.J):
+        got = H.unpack_block(Mh, plan.host, j, K)
+        ref = blocks[j]
+        if ref.size:
+            rel.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    rel = np.array(rel)
+    print(f"[assembly {dtype}] {name}: normwise relative error per block max {rel.max():.2e}, "
+          f"median {np.median(rel):.2e}", flush=True)
+    assert rel.max() <= (1e-3 if dtype == "f32" else 1e-2)
