@@ -155,7 +155,7 @@ def learned_study(args):
         y0 = Y0[:, b].contiguous()
         row = {}
         for name, kw in (("plain_fp64_cold", {}), ("plain_fp64_warm", {"y0": y0}),
-                         ("mixed_f32_warm", {"y0": y0, "inner_dtype": rfm.F32, "inner_tol": 1e-4})):
+                         ("mixed_f32_warm", {"y0": y0, "inner_dtype": rfm.F32})):
             torch.cuda.synchronize()
             ta = time.perf_counter()
             _, info = rfm.rfm_lsqr_solve(plan, fact, hb, atol=args.tol, btol=args.tol, maxit=args.maxit,
@@ -334,7 +334,7 @@ def main():
     ea.record()
     _, minfo = rfm.rfm_lsqr_solve(plan, fact, h, atol=args.tol, btol=args.tol, maxit=args.maxit,
                                   check_every=args.check_every, use_graph=0 if args.no_graph else 1, y=y, ws=ws,
-                                  inner_dtype=rfm.F32, inner_tol=1e-4)
+                                  inner_dtype=rfm.F32)
     eb.record()
     torch.cuda.synchronize()
     out["lsqr"]["mixed_f32_ms"] = ea.elapsed_time(eb)

@@ -233,7 +233,8 @@ typedef struct {
   double ms[5];           /* total ms of the stages: [0] forward block products (R form: with
                              the triangular solves), [1] row gather + beta, [2] adjoint block
                              products (R form: with the transposed solves), [3] alpha and the
-                             rotation, [4] y/w update + stop test */
+                             rotation (R form only; the Q form does them in stage 4 and leaves
+                             this 0), [4] y/w update + stop test */
   int64_t launches[5];    /* sampled launches counted (only iterations that did work) */
 } rfm_kernel_times;
 
@@ -284,13 +285,18 @@ size_t rfm_lsqr_ws_bytes(const rfm_layout *L);
  * solution.  After stopping the residuals are recomputed explicitly with the operator
  * and returned in info.
  * Precision form (opts->inner_dtype != RFM_F64): y <- y0; repeat { r = h - A y and A^T r in
- * binary64 with the full operator; stop by S1/S2 on these explicit values; solve
- * min ||A_low d - r|| by LSQR with atol = btol = inner_tol (A_low the narrow Q_hat, binary32
- * accumulation); y <- y + d } while ||A^T r|| at least halves per step (and for at most
- * max_outer steps); then binary64 LSQR from y (the finish) until S1/S2.  Refinement through a
+ * binary64 with the full operator; stop by S1/S2 on these explicit values; first step: LSQR
+ * on min ||A_low y - h|| from the current y, later steps: min ||A_low d - r|| from 0 and
+ * y <- y + d, both with atol = btol = inner_tol (A_low the narrow Q_hat, binary32
+ * accumulation) } while ||A^T r|| at least halves per step (and for at most max_outer
+ * steps); then binary64 LSQR from y (the finish) until S1/S2.  Refinement through a
  * narrow operator converges to A_low^T (h - A y) = 0, not A^T (h - A y) = 0, which on these
  * least-squares systems (non-zero optimal residual) leaves ||A^T r|| near u_low ||A|| ||r||;
- * the finish removes that bias.  opts->maxit caps all iterations together.
+ * the finish removes that bias.  opts->maxit caps all iterations together.  With
+ * inner_tol = atol = btol and max_outer = 1 the scheme is one narrow LSQR solve to the full
+ * rule, the binary64 check, and a binary64 finish only where that check fails: the Krylov
+ * process is never restarted, which matters on ill-conditioned systems where short inner
+ * solves each lose the subspace built so far.
  * Vectors: h device [N]; y0, y device [ncols] (entry (j,k) for k < r_j at feat_off[j]+k
  * in pivot order; other entries of y are set to 0).  A warm start whose residual
  * ||h - A y0|| exceeds ||h|| is discarded and the solve starts from 0 (info->warm_rejected).  (sync): returns after the solve;

@@ -76,7 +76,9 @@ class RefineInfo:
 def refine(A, A_low, h, y0=None, atol=1e-8, btol=1e-8, inner_tol=1e-4, max_outer=20,
            max_inner=100000, anorm=None, polish_maxit=100000):
     """Binary64 residual refinement around LSQR on the narrow operator, then a binary64
-    polish when the explicit ||A^T r|| stops falling."""
+    polish when the explicit ||A^T r|| stops falling (or after max_outer steps).  The first
+    step runs the narrow LSQR on h from the current y; later steps solve for a correction
+    of the binary64 residual."""
     if anorm is None:
         anorm = float(np.sqrt(A.n))
     y = np.zeros(A.n) if y0 is None else np.array(y0, dtype=np.float64, copy=True)
@@ -101,9 +103,15 @@ def refine(A, A_low, h, y0=None, atol=1e-8, btol=1e-8, inner_tol=1e-4, max_outer
         if info.outer >= max_outer or at > 0.5 * prev_at:
             break
         prev_at = at
-        d, inner = lsqr_mod.lsqr(A_low, r, atol=inner_tol, btol=inner_tol, maxit=max_inner, anorm=anorm)
+        if info.outer == 0:
+            # first step: the narrow solve on h itself from the current y, so its rule is taken
+            # relative to ||h|| and ||y|| (from y = 0 this is the correction solve on r = h)
+            y, inner = lsqr_mod.lsqr(A_low, h, y0=y, atol=inner_tol, btol=inner_tol, maxit=max_inner,
+                                     anorm=anorm)
+        else:
+            d, inner = lsqr_mod.lsqr(A_low, r, atol=inner_tol, btol=inner_tol, maxit=max_inner, anorm=anorm)
+            y = y + d
         info.inner_iters += inner.iters
-        y = y + d
         info.outer += 1
     y, pol = lsqr_mod.lsqr(A, h, y0=y, atol=atol, btol=btol, maxit=polish_maxit, anorm=anorm)
     info.polish_iters = pol.iters

@@ -4,23 +4,26 @@
 // Operator A = sum_j V_j^T Q_hat_j W_hat_j (Q form).  Vectors over columns use the
 // padded per-feature layout (entry (j,k) at feat_off[j] + k, k < r_j; the rest stay 0).
 //
-// One LSQR iteration = four data-parallel launches, each followed by a one-workgroup
-// reduction, on the caller's stream:
+// One LSQR iteration of the Q form = five launches on the caller's stream:
 //   fwd_local   t_(j,i) = sum_k Q_hat_j[i,k] v_j[k]       lane <-> row, coalesced column reads
 //   fwd_gather  p_r = sum_{j covering r} t_(j,r) - alpha u_r, summed in ascending j (no
 //               atomics, so the result does not depend on scheduling); ||p||^2 partials
-//               -> reduce_step: beta
+//   reduce_step beta
 //   adj_local   z_j = Q_hat_j^T (p / beta) over column tiles of I_j x r_j (the block's rows
 //               of p, copied contiguously by fwd_gather, staged in LDS once per
 //               workgroup), q = z - beta v; ||q||^2 partials
-//               -> reduce_step: alpha and the Givens-rotation scalar step of Paige-Saunders
-//   yw_update   y += (phi/rho) w, w = v - (theta/rho) w; ||y||^2 partials
-//               -> reduce_step: ||y|| and the stopping rule (raises the done flag)
-// Every grid-wide sum is a fixed-order sum of per-workgroup partials finished by a single
-// workgroup, so results are bitwise reproducible, and only that workgroup writes the
-// scalar state.  After the done flag is up every kernel returns at once, so the host
-// launches iterations in batches (optionally one captured HIP graph per batch) and only
-// reads the scalar state between batches.
+//   yw_update   alpha = sqrt(sum of the adjoint partials) and the Givens-rotation scalar step
+//               of Paige-Saunders, y += (phi/rho) w, w = v - (theta/rho) w; ||y||^2 partials
+//   reduce_step ||y|| and the stopping rule (raises the done flag)
+// Every grid-wide sum is a fixed-order sum of per-workgroup partials, so results are bitwise
+// reproducible.  A one-workgroup reduce_step finishes a sum and is the only writer of the
+// scalar state, except in yw_update, where every workgroup recomputes alpha from the
+// adjoint partials (identical instructions on identical data, so every workgroup holds the
+// same value) and one workgroup stores the scalars, in fields no workgroup of the same launch
+// reads.  The R form (transposed solves around the products) finishes alpha in a reduce_step
+// too.  After the done flag is up every kernel returns at once, so the host launches
+// iterations in batches (optionally one captured HIP graph per batch) and only reads the
+// scalar state between batches.
 #include <cmath>
 #include <vector>
 
@@ -33,6 +36,7 @@ struct State {
   double alpha, beta;      // alpha_i, beta_i of u_i = p/beta_i, v_i = q/alpha_i
   double beta_next;        // beta_{i+1} from the forward gather
   double rhobar, phibar;
+  double rhobar_n, phibar_n;  // the rotation's new values, promoted by the step that follows
   double phi_rho, theta_rho;
   double rnorm, artnorm, ynorm, hnorm, anorm;
   double atol, btol;
@@ -44,13 +48,49 @@ struct State {
 enum Mode : int { ITER = 0, INIT = 1, RESID = 2, COPYH = 3 };
 enum Flags : int { F_CHECK_DONE = 1, F_DIV_ALPHA = 2, F_DIV_BETA = 4, F_COMBINE = 8 };
 enum Reduce : int { R_BETA = 0, R_BETA_INIT = 1, R_ALPHA = 2, R_ALPHA_INIT = 3, R_Y = 4, R_Y_INIT = 5,
-                    R_CHK_R = 6, R_CHK_AT = 7 };
+                    R_CHK_R = 6, R_CHK_AT = 7, R_YF = 8 };
 
 constexpr int kRowTile = 256;
 constexpr int kAdjThreads = 256;
 constexpr int kVecThreads = 256;
 constexpr int kRedThreads = 1024;
 constexpr int kStages = 5;   // timed stages of one iteration (see rfm_kernel_times)
+
+// Givens rotation eliminating beta_{i+1} (Paige-Saunders recurrences), from rhobar_i,
+// phibar_i, alpha_{i+1} and beta_{i+1}.
+struct Rotation {
+  double rhobar, phibar, phi_rho, theta_rho, artnorm;
+};
+__device__ __forceinline__ Rotation givens(double rhobar, double phibar, double an, double bn) {
+  const double rho = hypot(rhobar, bn);
+  const double c = rhobar / rho;
+  const double sn = bn / rho;
+  const double theta = sn * an;
+  const double phi = c * phibar;
+  Rotation g;
+  g.rhobar = -c * an;
+  g.phibar = sn * phibar;
+  g.phi_rho = phi / rho;
+  g.theta_rho = theta / rho;
+  g.artnorm = g.phibar * an * fabs(c);
+  return g;
+}
+
+// Fixed-order sum of part[0..n) by one workgroup (four strided accumulators per thread, then
+// the workgroup sum); the result is in every thread.
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int64_t n, double *red) {
+  const int64_t s = blockDim.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + 3 * s < n; i += 4 * s) {
+    a0 += part[i];
+    a1 += part[i + s];
+    a2 += part[i + 2 * s];
+    a3 += part[i + 3 * s];
+  }
+  for (; i < n; i += s) a0 += part[i];
+  return block_sum((a0 + a1) + (a2 + a3), red);
+}
 
 __global__ void fill_zero(double *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -186,10 +226,6 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const T *
   const int r = rank[j];
   const int k0 = blockIdx.x * ct;
   const int64_t pidx = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  if (k0 >= r) {
-    if (threadIdx.x == 0) part[pidx] = 0.0;
-    return;
-  }
   const int k1 = min(r, k0 + ct);
   const int64_t r0 = L.row_off[j];
   const int m = (int)(L.row_off[j + 1] - r0);
@@ -197,6 +233,10 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const T *
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const double bn = st->beta_next;
+  if (k0 >= r) {
+    if (threadIdx.x == 0) part[pidx] = 0.0;
+    return;
+  }
   const double alpha = st->alpha;
   A *us = (A *)smem;
   int *ks = (int *)(smem + L.max_rows);
@@ -379,23 +419,49 @@ __global__ __launch_bounds__(kTriThreads) void trsv_upper_t(rfm_layout L, const 
 }
 
 // ITER: y += (phi/rho) w ; w = v - (theta/rho) w with v = q / alpha.   INIT: w = q / alpha.
-// Per-workgroup partials of ||y||^2.
+// With apart (ITER, Q form) every workgroup forms alpha from the napart adjoint partials and
+// performs the rotation itself; the first workgroup stores the scalars (the rotation's
+// rhobar / phibar in the _n fields, promoted by the R_YF step).  Per-workgroup partials of
+// ||y||^2.
 __global__ __launch_bounds__(kVecThreads) void yw_update(int64_t n, const double *__restrict__ qnew,
                                                          double *__restrict__ w,
                                                          double *__restrict__ y, double *part,
-                                                         const State *st, int mode) {
+                                                         State *st, int mode,
+                                                         const double *__restrict__ apart, int64_t napart) {
   __shared__ double red[kVecThreads / kWave];
   if (st->done && mode == ITER) return;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double a = st->alpha;
+  double a, phr, thr;
+  if (mode == ITER && apart) {
+    const double an = sqrt(sum_partials(apart, napart, red));
+    const double bn = st->beta_next;
+    const Rotation g = givens(st->rhobar, st->phibar, an, bn);
+    a = an;
+    phr = g.phi_rho;
+    thr = g.theta_rho;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->alpha = an;
+      st->beta = bn;
+      st->rhobar_n = g.rhobar;
+      st->phibar_n = g.phibar;
+      st->phi_rho = g.phi_rho;
+      st->theta_rho = g.theta_rho;
+      st->rnorm = g.phibar;
+      st->artnorm = g.artnorm;
+    }
+  } else {
+    a = st->alpha;
+    phr = st->phi_rho;
+    thr = st->theta_rho;
+  }
   double yy = 0.0;
   if (k < n) {
     const double v = (a > 0.0) ? qnew[k] / a : 0.0;
     if (mode == ITER) {
       const double wk = w[k];
-      const double yk = y[k] + st->phi_rho * wk;
+      const double yk = y[k] + phr * wk;
       y[k] = yk;
-      w[k] = v - st->theta_rho * wk;
+      w[k] = v - thr * wk;
       yy = yk * yk;
     } else {
       w[k] = v;
@@ -412,7 +478,7 @@ __global__ __launch_bounds__(kVecThreads) void yw_update(int64_t n, const double
 __global__ __launch_bounds__(kRedThreads) void reduce_step(const double *part, int64_t n,
                                                            const double *part2, State *st, int what) {
   __shared__ double red[kRedThreads / kWave];
-  if ((what == R_BETA || what == R_ALPHA || what == R_Y) && st->done) return;
+  if ((what == R_BETA || what == R_ALPHA || what == R_Y || what == R_YF) && st->done) return;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += kRedThreads) s += part[i];
   s = block_sum(s, red);
@@ -446,19 +512,14 @@ __global__ __launch_bounds__(kRedThreads) void reduce_step(const double *part, i
       break;
     }
     case R_ALPHA: {
-      // Givens rotation eliminating beta_{i+1} (Paige-Saunders recurrences)
       const double an = sqrt(s), bn = st->beta_next;
-      const double rho = hypot(st->rhobar, bn);
-      const double c = st->rhobar / rho;
-      const double sn = bn / rho;
-      const double theta = sn * an;
-      const double phi = c * st->phibar;
-      st->rhobar = -c * an;
-      st->phibar = sn * st->phibar;
-      st->phi_rho = phi / rho;
-      st->theta_rho = theta / rho;
-      st->rnorm = st->phibar;
-      st->artnorm = st->phibar * an * fabs(c);
+      const Rotation g = givens(st->rhobar, st->phibar, an, bn);
+      st->rhobar = g.rhobar;
+      st->phibar = g.phibar;
+      st->phi_rho = g.phi_rho;
+      st->theta_rho = g.theta_rho;
+      st->rnorm = g.phibar;
+      st->artnorm = g.artnorm;
       st->alpha = an;
       st->beta = bn;
       break;
@@ -466,6 +527,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_step(const double *part, i
     case R_Y_INIT:
       st->ynorm = sqrt(s);
       break;
+    case R_YF:  // the rotation of the fused update becomes the current one
+      st->rhobar = st->rhobar_n;
+      st->phibar = st->phibar_n;
+      [[fallthrough]];
     case R_Y: {
       st->ynorm = sqrt(s);
       st->iter += 1;
@@ -555,7 +620,7 @@ __global__ __launch_bounds__(kVecThreads) void sq_partials(int64_t n, const doub
 }
 
 struct Work {
-  double *t, *ub, *p[2], *res, *q[2], *w, *z, *xs, *zs, *dy, *part, *part2;
+  double *t, *ub, *p[2], *res, *q[2], *w, *z, *xs, *zs, *dy, *part, *part2, *part3;
   State *st, *st2;
   int64_t npart;
 };
@@ -604,6 +669,7 @@ size_t carve(const rfm_layout *L, char *base, Work *W) {
   w.dy = (double *)take(sizeof(double) * nc);
   w.part = (double *)take(sizeof(double) * npart);
   w.part2 = (double *)take(sizeof(double) * npart);
+  w.part3 = (double *)take(sizeof(double) * npart);
   w.st = (State *)take(sizeof(State));
   w.st2 = (State *)take(sizeof(State));
   w.npart = npart;
@@ -631,6 +697,8 @@ struct Launcher {
   unsigned g_cols() const { return ceil_div(L->ncols, kVecThreads); }
   unsigned g_adj_x() const { return ceil_div(L->max_cols > 0 ? L->max_cols : 1, ct); }
   int64_t n_adj_part() const { return rform ? (int64_t)L->J : (int64_t)g_adj_x() * L->J; }
+  // Q form iterations take alpha and the rotation inside yw_update (see the file comment)
+  bool fused() const { return !rform; }
 
   // t = A_local v (per-incidence block products); v = vin / alpha in ITER mode
   void fwd(hipStream_t s, const double *vin, State *st, int mode) {
@@ -666,17 +734,19 @@ struct Launcher {
     int flags = 0;
     if (mode == ITER) flags = F_CHECK_DONE | F_DIV_BETA | F_COMBINE;
     if (mode == INIT) flags = F_DIV_BETA;
+    // fused: the adjoint partials go to W.part3, where yw_update sums them
+    double *pout = (mode == ITER && fused()) ? W.part3 : W.part;
     const dim3 grid(g_adj_x(), L->J);
     const int32_t *nk = nullptr;
     if (!rform && dtype == RFM_F32) {
       hipLaunchKernelGGL((adj_local<float, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
-                         (const float *)Qlow, nk, A->rank, ubk, qcur, qnew, W.part, ct, st, flags);
+                         (const float *)Qlow, nk, A->rank, ubk, qcur, qnew, pout, ct, st, flags);
     } else if (!rform && dtype == RFM_BF16) {
       hipLaunchKernelGGL((adj_local<bf16_t, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
-                         (const bf16_t *)Qlow, nk, A->rank, ubk, qcur, qnew, W.part, ct, st, flags);
+                         (const bf16_t *)Qlow, nk, A->rank, ubk, qcur, qnew, pout, ct, st, flags);
     } else if (!rform) {
       hipLaunchKernelGGL((adj_local<double, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->Q,
-                         nk, A->rank, ubk, qcur, qnew, W.part, ct, st, flags);
+                         nk, A->rank, ubk, qcur, qnew, pout, ct, st, flags);
     } else {
       hipLaunchKernelGGL((adj_local<double, true>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->M, A->kept,
                          A->rank, ubk, qcur, W.zs, W.part, ct, st, flags & ~F_COMBINE);
@@ -685,15 +755,19 @@ struct Launcher {
     }
   }
   void yw(hipStream_t s, const double *qnew, double *y, State *st, int mode) {
+    // fused: alpha and the rotation from the adjoint partials (W.part3)
+    const bool fz = (mode == ITER && fused());
     hipLaunchKernelGGL(yw_update, dim3(g_cols()), dim3(kVecThreads), 0, s, L->ncols, qnew, W.w, y,
-                       W.part, st, mode);
+                       W.part, st, mode, fz ? (const double *)W.part3 : nullptr, fz ? n_adj_part() : (int64_t)0);
   }
   void reduce(hipStream_t s, int64_t n, State *st, int what) {
     hipLaunchKernelGGL(reduce_step, dim3(1), dim3(kRedThreads), 0, s, W.part, n, W.part2, st, what);
   }
-  // ev (nullable): 6 events around the five stages of one iteration
+  // ev (nullable): 6 events around the five stages of one iteration (the fused Q form has
+  // no separate alpha / rotation stage: ev[3] and ev[4] are recorded back to back)
   void iteration(hipStream_t s, int64_t i, double *y, hipEvent_t *ev) {
     const int a = (int)((i - 1) & 1), b = (int)(i & 1);
+    const bool fz = fused();
     if (ev) hipEventRecord(ev[0], s);
     fwd(s, W.q[a], W.st, ITER);
     if (ev) hipEventRecord(ev[1], s);
@@ -702,10 +776,10 @@ struct Launcher {
     if (ev) hipEventRecord(ev[2], s);
     adj(s, W.p[b], W.q[a], W.q[b], W.st, ITER);
     if (ev) hipEventRecord(ev[3], s);
-    reduce(s, n_adj_part(), W.st, R_ALPHA);
+    if (!fz) reduce(s, n_adj_part(), W.st, R_ALPHA);
     if (ev) hipEventRecord(ev[4], s);
     yw(s, W.q[b], y, W.st, ITER);
-    reduce(s, g_cols(), W.st, R_Y);
+    reduce(s, g_cols(), W.st, fz ? R_YF : R_Y);
     if (ev) hipEventRecord(ev[5], s);
   }
 };
@@ -823,6 +897,7 @@ rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, doub
     // sampled iterations that did work (later launches return at once after the stop)
     for (int64_t b = 0; b < sampled && first + b <= hs.iter; ++b)
       for (int k = 0; k < kStages; ++k) {
+        if (k == 3 && X.fused()) continue;  // no separate alpha / rotation launch
         float ms = 0.f;
         const size_t e0 = (size_t)(kStages + 1) * b + k;
         RFM_HIP_TRY(hipEventElapsedTime(&ms, pool.ev[e0], pool.ev[e0 + 1]));
@@ -969,13 +1044,24 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
       prev_at = hc.artnorm;
       State hi{};
       const int64_t cap = opts->max_inner < budget ? opts->max_inner : budget;
-      s = run_lsqr(Xl, anorm, nullptr, X.W.dy, opts->inner_tol, opts->inner_tol, cap, opts->check_every,
-                   opts->use_graph != 0, opts->times, nullptr, st, &hi);
+      if (outer == 0) {
+        // first step: the narrow LSQR on h itself from the current y (in place), so its rule is
+        // relative to ||h|| and ||y||; from y = 0 this is the correction solve on r = h
+        Launcher Xh = Xl;
+        Xh.h = h;
+        s = run_lsqr(Xh, anorm, y, y, opts->inner_tol, opts->inner_tol, cap, opts->check_every,
+                     opts->use_graph != 0, opts->times, nullptr, st, &hi);
+      } else {
+        s = run_lsqr(Xl, anorm, nullptr, X.W.dy, opts->inner_tol, opts->inner_tol, cap, opts->check_every,
+                     opts->use_graph != 0, opts->times, nullptr, st, &hi);
+        if (s == RFM_OK) {
+          hipLaunchKernelGGL(axpy_inplace, dim3(ceil_div(L->ncols, 256)), dim3(256), 0, st, L->ncols, X.W.dy, y);
+          RFM_LAUNCH_CHECK();
+        }
+      }
       if (s != RFM_OK) return s;
       inner_total += hi.iter;
       budget -= hi.iter;
-      hipLaunchKernelGGL(axpy_inplace, dim3(ceil_div(L->ncols, 256)), dim3(256), 0, st, L->ncols, X.W.dy, y);
-      RFM_LAUNCH_CHECK();
     }
     int64_t polish_iters = 0;
     if (polish) {

@@ -332,9 +332,15 @@ def rfm_pack_q(plan: Plan, fact: dict, dtype, Qlow=None):
 
 def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, maxit=10000,
                    check_every=16, use_graph=0, form=FORM_Q, y=None, ws=None, times=None,
-                   history=None, inner_dtype=F64, max_outer=20, max_inner=100000, inner_tol=1e-4,
+                   history=None, inner_dtype=F64, max_outer=1, max_inner=None, inner_tol=None,
                    adj_tile=0):
+    """Precision form defaults: one narrow solve to the caller's rule (inner_tol = atol, all
+    of maxit), then the binary64 check and finish."""
     L = plan.layout
+    if max_inner is None:
+        max_inner = maxit
+    if inner_tol is None:
+        inner_tol = atol if 0.0 < atol < 1.0 else 1e-8
     dev = h.device
     y = torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if y is None else y
     qlow = fact.get("Qlow")
