@@ -52,6 +52,8 @@ enum Reduce : int { R_BETA = 0, R_BETA_INIT = 1, R_ALPHA = 2, R_ALPHA_INIT = 3, 
 
 constexpr int kRowTile = 256;
 constexpr int kAdjThreads = 256;
+constexpr int kAdjCols = 4;    // adjoint products: columns per wave ...
+constexpr int kAdjChunks = 2;  // ... and rows chunks of 64 per step (kAdjCols x kAdjChunks loads in flight)
 constexpr int kVecThreads = 256;
 constexpr int kRedThreads = 1024;
 constexpr int kStages = 5;   // timed stages of one iteration (see rfm_kernel_times)
@@ -92,6 +94,27 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ part, 
   return block_sum((a0 + a1) + (a2 + a3), red);
 }
 
+// Per-block operands of the block products, gathered once per solve so that a workgroup
+// reads them with one scalar load issued together with the state's: the block's first row
+// and first feature, its offset in the operand storage, its rows m_j and kept columns r_j.
+struct alignas(32) BlockDesc {
+  int64_t r0, f0, base;
+  int32_t m, r;
+};
+static_assert(sizeof(BlockDesc) == 32, "one 32-byte scalar load per block");
+
+__global__ void block_desc(rfm_layout L, const int32_t *__restrict__ rank, BlockDesc *__restrict__ d) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= L.J) return;
+  BlockDesc b;
+  b.r0 = L.row_off[j];
+  b.f0 = L.feat_off[j];
+  b.base = L.blk_off[j];
+  b.m = (int32_t)(L.row_off[j + 1] - L.row_off[j]);
+  b.r = rank[j];
+  d[j] = b;
+}
+
 __global__ void fill_zero(double *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -130,22 +153,22 @@ __device__ __forceinline__ const T *operand_col(const T *Op, int64_t base, const
 template <typename T, bool KEPT>
 __global__ __launch_bounds__(kRowTile) void fwd_local(rfm_layout L, const T *__restrict__ Op,
                                                       const int32_t *__restrict__ kept,
-                                                      const int32_t *__restrict__ rank,
+                                                      const BlockDesc *__restrict__ desc,
                                                       const double *__restrict__ vin,
                                                       double *__restrict__ t, const State *st,
                                                       int flags) {
   using A = typename Acc<T>::type;
   extern __shared__ double smem[];
-  if ((flags & F_CHECK_DONE) && st->done) return;
   const int j = blockIdx.y;
-  const int64_t r0 = L.row_off[j];
-  const int m = (int)(L.row_off[j + 1] - r0);
-  if ((int)blockIdx.x * kRowTile >= m) return;
-  const int64_t f0 = L.feat_off[j];
-  const int r = rank[j];
+  // the descriptor and the state are loaded before the first branch: one round trip
+  const BlockDesc d = desc[j];
+  const int dn = st->done;
+  const double alpha = (flags & F_DIV_ALPHA) ? st->alpha : 1.0;
+  if (((flags & F_CHECK_DONE) && dn) || (int)blockIdx.x * kRowTile >= d.m) return;
+  const int64_t r0 = d.r0, f0 = d.f0;
+  const int m = d.m, r = d.r;
   A *vs = (A *)smem;
   int *ks = (int *)(smem + L.max_cols);
-  const double alpha = (flags & F_DIV_ALPHA) ? st->alpha : 1.0;
   for (int k = threadIdx.x; k < r; k += kRowTile) {
     vs[k] = (A)((flags & F_DIV_ALPHA) ? vin[f0 + k] / alpha : vin[f0 + k]);
     if (KEPT) ks[k] = kept[f0 + k];
@@ -153,7 +176,7 @@ __global__ __launch_bounds__(kRowTile) void fwd_local(rfm_layout L, const T *__r
   __syncthreads();
   const int i = blockIdx.x * kRowTile + threadIdx.x;
   if (i >= m) return;
-  const int64_t base = L.blk_off[j] + i;
+  const int64_t base = d.base + i;
   // eight independent accumulators: eight loads in flight per thread
   A acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int k = 0;
@@ -206,13 +229,13 @@ __global__ __launch_bounds__(kVecThreads) void fwd_gather(rfm_layout L, const do
 
 // z_j = Op_j^T u_{I_j} over a tile of ct columns of block j, u = p / beta_next (F_DIV_BETA)
 // or p, with p in the block-row layout (ub, written by fwd_gather); with F_COMBINE
-// q = z - beta_next * (qcur / alpha), else q = z.  Each wave takes 4 columns at a time; the
-// block's rows of u are staged in LDS once per workgroup.  One partial of sum q^2 per
-// workgroup.
+// q = z - beta_next * (qcur / alpha), else q = z.  Each wave takes kAdjCols columns at a time and
+// reads u with the columns (no LDS staging; the R form stages its kept indices).  One
+// partial of sum q^2 per workgroup.
 template <typename T, bool KEPT>
 __global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const T *__restrict__ Op,
                                                          const int32_t *__restrict__ kept,
-                                                         const int32_t *__restrict__ rank,
+                                                         const BlockDesc *__restrict__ desc,
                                                          const double *__restrict__ ub,
                                                          const double *__restrict__ qcur,
                                                          double *__restrict__ qnew, double *part,
@@ -220,77 +243,84 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local(rfm_layout L, const T *
   using A = typename Acc<T>::type;
   extern __shared__ double smem[];
   __shared__ double colsum[kAdjThreads / kWave];
-  if ((flags & F_CHECK_DONE) && st->done) return;
   constexpr int NW = kAdjThreads / kWave;
   const int j = blockIdx.y;
-  const int r = rank[j];
   const int k0 = blockIdx.x * ct;
   const int64_t pidx = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  const int k1 = min(r, k0 + ct);
-  const int64_t r0 = L.row_off[j];
-  const int m = (int)(L.row_off[j + 1] - r0);
-  const int64_t f0 = L.feat_off[j];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
-  const double bn = st->beta_next;
-  if (k0 >= r) {
-    if (threadIdx.x == 0) part[pidx] = 0.0;
+  // the descriptor and the state are loaded before the first branch: one round trip
+  const BlockDesc d = desc[j];
+  const int dn = st->done;
+  const double bn = st->beta_next, alpha = st->alpha;
+  const bool stop = (flags & F_CHECK_DONE) && dn;
+  if (stop || k0 >= d.r) {
+    if (!stop && threadIdx.x == 0) part[pidx] = 0.0;
     return;
   }
-  const double alpha = st->alpha;
-  A *us = (A *)smem;
-  int *ks = (int *)(smem + L.max_rows);
-  for (int i = threadIdx.x; i < m; i += kAdjThreads) {
-    const double p = ub[r0 + i];
-    us[i] = (A)((flags & F_DIV_BETA) ? (bn > 0.0 ? p / bn : 0.0) : p);
-  }
-  if (KEPT)
+  const int r = d.r, m = d.m;
+  const int k1 = min(r, k0 + ct);
+  const int64_t r0 = d.r0, f0 = d.f0;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  int *ks = (int *)smem;
+  if (KEPT) {
     for (int k = k0 + threadIdx.x; k < k1; k += kAdjThreads) ks[k - k0] = kept[f0 + k];
-  __syncthreads();
-  const int64_t base = L.blk_off[j];
+    __syncthreads();
+  }
+  // u_i read where it is used (the block's rows of p are contiguous in ub and shared by the
+  // block's workgroups through the caches), so the column loads start without a barrier
+  const double *__restrict__ pu = ub + r0;
+  const bool divb = (flags & F_DIV_BETA) != 0;
+  auto uval = [&](int i) -> A {
+    const double p = pu[i];
+    return (A)(divb ? (bn > 0.0 ? p / bn : 0.0) : p);
+  };
+  const int64_t base = d.base;
   double ssq = 0.0;
-  for (int k = k0 + 4 * wid; k < k1; k += 4 * NW) {
-    // column k of the tile: Q_hat_j[:, k], or M_j[:, kept_k] with kept_k staged at ks[k - k0]
-    auto col = [&](int kk) { return Op + base + (int64_t)(KEPT ? ks[kk - k0] : kk) * m; };
-    const T *__restrict__ c0 = col(k);
-    const T *__restrict__ c1 = col(min(k + 1, k1 - 1));
-    const T *__restrict__ c2 = col(min(k + 2, k1 - 1));
-    const T *__restrict__ c3 = col(min(k + 3, k1 - 1));
-    A a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    A b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+  for (int k = k0 + kAdjCols * wid; k < k1; k += kAdjCols * NW) {
+    // column k + c of the tile: Q_hat_j[:, k + c], or M_j[:, kept] with the kept index staged
+    // at ks[k + c - k0]; past the tile's end the last column is read again (and not stored)
+    const T *__restrict__ cp[kAdjCols];
+#pragma unroll
+    for (int c = 0; c < kAdjCols; ++c) {
+      const int kk = min(k + c, k1 - 1);
+      cp[c] = Op + base + (int64_t)(KEPT ? ks[kk - k0] : kk) * m;
+    }
+    A acc[kAdjCols][kAdjChunks];
+#pragma unroll
+    for (int c = 0; c < kAdjCols; ++c)
+#pragma unroll
+      for (int h = 0; h < kAdjChunks; ++h) acc[c][h] = 0;
     int i = lane;
-    for (; i + kWave < m; i += 2 * kWave) {
-      const A u0 = us[i], u1 = us[i + kWave];
-      a0 += (A)widen(c0[i]) * u0;
-      a1 += (A)widen(c1[i]) * u0;
-      a2 += (A)widen(c2[i]) * u0;
-      a3 += (A)widen(c3[i]) * u0;
-      b0 += (A)widen(c0[i + kWave]) * u1;
-      b1 += (A)widen(c1[i + kWave]) * u1;
-      b2 += (A)widen(c2[i + kWave]) * u1;
-      b3 += (A)widen(c3[i + kWave]) * u1;
+    for (; i + (kAdjChunks - 1) * kWave < m; i += kAdjChunks * kWave) {
+#pragma unroll
+      for (int h = 0; h < kAdjChunks; ++h) {
+        const A u = uval(i + h * kWave);
+#pragma unroll
+        for (int c = 0; c < kAdjCols; ++c) acc[c][h] += (A)widen(cp[c][i + h * kWave]) * u;
+      }
     }
-    if (i < m) {
-      const A u0 = us[i];
-      a0 += (A)widen(c0[i]) * u0;
-      a1 += (A)widen(c1[i]) * u0;
-      a2 += (A)widen(c2[i]) * u0;
-      a3 += (A)widen(c3[i]) * u0;
+    for (; i < m; i += kWave) {
+      const A u = uval(i);
+#pragma unroll
+      for (int c = 0; c < kAdjCols; ++c) acc[c][0] += (A)widen(cp[c][i]) * u;
     }
-    const double z[4] = {wave_sum_dpp((double)(a0 + b0)), wave_sum_dpp((double)(a1 + b1)),
-                         wave_sum_dpp((double)(a2 + b2)), wave_sum_dpp((double)(a3 + b3))};
-    if (lane < 4 && k + lane < k1) {
-      double zz = z[0];
-      if (lane == 1) zz = z[1];
-      if (lane == 2) zz = z[2];
-      if (lane == 3) zz = z[3];
+    double z = 0.0;  // lane c < kAdjCols keeps the sum of column k + c
+#pragma unroll
+    for (int c = 0; c < kAdjCols; ++c) {
+      A t = acc[c][0];
+#pragma unroll
+      for (int h = 1; h < kAdjChunks; ++h) t += acc[c][h];
+      const double zc = wave_sum_dpp((double)t);
+      if (lane == c) z = zc;
+    }
+    if (lane < kAdjCols && k + lane < k1) {
       const int kk = k + lane;
-      const double q = (flags & F_COMBINE) ? zz - bn * (qcur[f0 + kk] / alpha) : zz;
+      const double q = (flags & F_COMBINE) ? z - bn * (qcur[f0 + kk] / alpha) : z;
       qnew[f0 + kk] = q;
       ssq += q * q;
     }
   }
-  // lanes 0..3 hold the squares of their columns; sum them in lane order
+  // lanes 0..kAdjCols-1 hold the squares of their columns; sum them in lane order
   ssq = wave_sum(ssq);
   if (lane == 0) colsum[wid] = ssq;
   __syncthreads();
@@ -621,6 +651,7 @@ __global__ __launch_bounds__(kVecThreads) void sq_partials(int64_t n, const doub
 
 struct Work {
   double *t, *ub, *p[2], *res, *q[2], *w, *z, *xs, *zs, *dy, *part, *part2, *part3;
+  BlockDesc *desc;
   State *st, *st2;
   int64_t npart;
 };
@@ -628,22 +659,23 @@ struct Work {
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Column tile of the adjoint products: about 4096 workgroups in total, tiles a multiple
-// of 16 columns (4 waves x 4 columns).
+// of kAdjQuantum columns (every wave of the workgroup takes kAdjCols columns).
+constexpr int kAdjQuantum = kAdjCols * (kAdjThreads / kWave);
 int adj_tile(const rfm_layout *L) {
   const int64_t mc = L->max_cols > 0 ? L->max_cols : 1;
   int64_t tiles = (4096 + L->J - 1) / L->J;
-  const int64_t max_tiles = (mc + 15) / 16;
+  const int64_t max_tiles = (mc + kAdjQuantum - 1) / kAdjQuantum;
   if (tiles > max_tiles) tiles = max_tiles;
   if (tiles < 1) tiles = 1;
   const int64_t per = (mc + tiles - 1) / tiles;
-  return (int)(((per + 15) / 16) * 16);
+  return (int)(((per + kAdjQuantum - 1) / kAdjQuantum) * kAdjQuantum);
 }
 
 size_t carve(const rfm_layout *L, char *base, Work *W) {
   const int64_t N = L->N, nc = L->ncols;
   const int64_t g_rows = (N + kVecThreads - 1) / kVecThreads;
   const int64_t g_cols = (nc + kVecThreads - 1) / kVecThreads;
-  const int ct = 16;  // smallest allowed adjoint tile: the most partials
+  const int ct = kAdjQuantum;  // smallest allowed adjoint tile: the most partials
   const int64_t g_adj = (int64_t)L->J * (((L->max_cols > 0 ? L->max_cols : 1) + ct - 1) / ct);
   int64_t npart = g_rows;
   if (g_cols > npart) npart = g_cols;
@@ -655,6 +687,7 @@ size_t carve(const rfm_layout *L, char *base, Work *W) {
     return p;
   };
   Work w{};
+  w.desc = (BlockDesc *)take(sizeof(BlockDesc) * (size_t)L->J);
   w.t = (double *)take(sizeof(double) * (size_t)L->nnz_rows);
   w.ub = (double *)take(sizeof(double) * (size_t)L->nnz_rows);
   w.p[0] = (double *)take(sizeof(double) * N);
@@ -688,10 +721,7 @@ struct Launcher {
   const void *Qlow = nullptr;  // RFM_F32 / RFM_BF16 copy of Q_hat in the block layout
 
   size_t fwd_lds() const { return (size_t)(L->max_cols > 0 ? L->max_cols : 1) * (sizeof(double) + sizeof(int)); }
-  size_t adj_lds() const {
-    return sizeof(double) * (size_t)(L->max_rows > 0 ? L->max_rows : 1) +
-           sizeof(int) * (size_t)(L->max_cols > 0 ? L->max_cols : 1);
-  }
+  size_t adj_lds() const { return rform ? sizeof(int) * (size_t)(L->max_cols > 0 ? L->max_cols : 1) : 0; }
   size_t tri_lds() const { return sizeof(double) * ((size_t)(L->max_cols > 0 ? L->max_cols : 1) + kTri * kTri); }
   unsigned g_rows() const { return ceil_div(L->N, kVecThreads); }
   unsigned g_cols() const { return ceil_div(L->ncols, kVecThreads); }
@@ -708,18 +738,18 @@ struct Launcher {
     const int32_t *nk = nullptr;
     if (!rform && dtype == RFM_F32) {
       hipLaunchKernelGGL((fwd_local<float, false>), grid, dim3(kRowTile), fwd_lds(), s, *L,
-                         (const float *)Qlow, nk, A->rank, vin, W.t, st, flags);
+                         (const float *)Qlow, nk, W.desc, vin, W.t, st, flags);
     } else if (!rform && dtype == RFM_BF16) {
       hipLaunchKernelGGL((fwd_local<bf16_t, false>), grid, dim3(kRowTile), fwd_lds(), s, *L,
-                         (const bf16_t *)Qlow, nk, A->rank, vin, W.t, st, flags);
+                         (const bf16_t *)Qlow, nk, W.desc, vin, W.t, st, flags);
     } else if (!rform) {
       hipLaunchKernelGGL((fwd_local<double, false>), grid, dim3(kRowTile), fwd_lds(), s, *L, A->Q,
-                         nk, A->rank, vin, W.t, st, flags);
+                         nk, W.desc, vin, W.t, st, flags);
     } else {
       hipLaunchKernelGGL(trsv_upper, dim3(L->J), dim3(kTriThreads), tri_lds(), s, *L, A->rank, A->R, vin,
                          W.xs, st, flags);
       hipLaunchKernelGGL((fwd_local<double, true>), grid, dim3(kRowTile), fwd_lds(), s, *L, A->M, A->kept,
-                         A->rank, W.xs, W.t, st, flags & F_CHECK_DONE);
+                         W.desc, W.xs, W.t, st, flags & F_CHECK_DONE);
     }
   }
   void gather(hipStream_t s, const double *pcur, double *pnew, State *st, int mode) {
@@ -740,16 +770,16 @@ struct Launcher {
     const int32_t *nk = nullptr;
     if (!rform && dtype == RFM_F32) {
       hipLaunchKernelGGL((adj_local<float, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
-                         (const float *)Qlow, nk, A->rank, ubk, qcur, qnew, pout, ct, st, flags);
+                         (const float *)Qlow, nk, W.desc, ubk, qcur, qnew, pout, ct, st, flags);
     } else if (!rform && dtype == RFM_BF16) {
       hipLaunchKernelGGL((adj_local<bf16_t, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
-                         (const bf16_t *)Qlow, nk, A->rank, ubk, qcur, qnew, pout, ct, st, flags);
+                         (const bf16_t *)Qlow, nk, W.desc, ubk, qcur, qnew, pout, ct, st, flags);
     } else if (!rform) {
       hipLaunchKernelGGL((adj_local<double, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->Q,
-                         nk, A->rank, ubk, qcur, qnew, pout, ct, st, flags);
+                         nk, W.desc, ubk, qcur, qnew, pout, ct, st, flags);
     } else {
       hipLaunchKernelGGL((adj_local<double, true>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->M, A->kept,
-                         A->rank, ubk, qcur, W.zs, W.part, ct, st, flags & ~F_COMBINE);
+                         W.desc, ubk, qcur, W.zs, W.part, ct, st, flags & ~F_COMBINE);
       hipLaunchKernelGGL(trsv_upper_t, dim3(L->J), dim3(kTriThreads), tri_lds(), s, *L, A->rank, A->R, W.zs,
                          qcur, qnew, W.part, st, flags & (F_CHECK_DONE | F_COMBINE));
     }
@@ -974,7 +1004,7 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
       return fail(RFM_EINVAL, "rfm_lsqr_solve: bad refinement options");
   }
   if (ws_bytes < rfm_lsqr_ws_bytes(L) || !ws) return fail(RFM_EINVAL, "rfm_lsqr_solve: workspace too small");
-  if ((size_t)L->max_rows * sizeof(double) + (size_t)L->max_cols * sizeof(int) > 120 * 1024 ||
+  if ((size_t)L->max_cols * (sizeof(double) + sizeof(int)) > 120 * 1024 ||
       ((size_t)L->max_cols + kTri * kTri) * sizeof(double) > 120 * 1024)
     return fail(RFM_EUNSUPPORTED, "rfm_lsqr_solve: block too large for LDS staging");
   hipStream_t st = (hipStream_t)stream;
@@ -983,9 +1013,11 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   X.L = L;
   X.A = A;
   X.h = h;
-  X.ct = opts->adj_tile > 0 ? ((opts->adj_tile + 15) / 16) * 16 : adj_tile(L);
+  X.ct = opts->adj_tile > 0 ? ((opts->adj_tile + kAdjQuantum - 1) / kAdjQuantum) * kAdjQuantum : adj_tile(L);
   X.rform = (A->form == RFM_FORM_R);
   carve(L, (char *)ws, &X.W);
+  hipLaunchKernelGGL(block_desc, dim3(ceil_div(L->J, 256)), dim3(256), 0, st, *L, A->rank, X.W.desc);
+  RFM_LAUNCH_CHECK();
 
   // ||A||_F = sqrt(sum_j r_j): the Q form has unit-norm columns
   std::vector<int32_t> hrank(L->J);
