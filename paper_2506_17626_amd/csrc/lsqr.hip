@@ -25,7 +25,10 @@
 // iterations in batches (optionally one captured HIP graph per batch) and only reads the
 // scalar state between batches.
 #include <cmath>
+#include <cstdint>
 #include <vector>
+
+#include <hip/hip_ext.h>
 
 #include "common.hpp"
 
@@ -710,6 +713,18 @@ size_t carve(const rfm_layout *L, char *base, Work *W) {
   return off;
 }
 
+// Kernel launch that, when given events, has the runtime stamp them with the kernel's own
+// start and end (the dispatch's timestamps, as a profiler sees them), not the time at which
+// the stream reached the event.
+template <typename F, typename... Args>
+void launch(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+            Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, s, e0, e1, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 struct Launcher {
   const rfm_layout *L;
   const rfm_operator *A;
@@ -730,36 +745,42 @@ struct Launcher {
   // Q form iterations take alpha and the rotation inside yw_update (see the file comment)
   bool fused() const { return !rform; }
 
+  // Each stage below takes optional events: e0 is stamped at the start of its first kernel,
+  // e1 at the end of its last.
+
   // t = A_local v (per-incidence block products); v = vin / alpha in ITER mode
-  void fwd(hipStream_t s, const double *vin, State *st, int mode) {
+  void fwd(hipStream_t s, const double *vin, State *st, int mode, hipEvent_t e0 = nullptr,
+           hipEvent_t e1 = nullptr) {
     if (L->max_rows <= 0) return;
     const int flags = (mode == ITER) ? (F_CHECK_DONE | F_DIV_ALPHA) : 0;
     const dim3 grid(ceil_div(L->max_rows, kRowTile), L->J);
     const int32_t *nk = nullptr;
     if (!rform && dtype == RFM_F32) {
-      hipLaunchKernelGGL((fwd_local<float, false>), grid, dim3(kRowTile), fwd_lds(), s, *L,
-                         (const float *)Qlow, nk, W.desc, vin, W.t, st, flags);
+      launch(fwd_local<float, false>, grid, dim3(kRowTile), fwd_lds(), s, e0, e1, *L, (const float *)Qlow, nk,
+             (const BlockDesc *)W.desc, vin, W.t, (const State *)st, flags);
     } else if (!rform && dtype == RFM_BF16) {
-      hipLaunchKernelGGL((fwd_local<bf16_t, false>), grid, dim3(kRowTile), fwd_lds(), s, *L,
-                         (const bf16_t *)Qlow, nk, W.desc, vin, W.t, st, flags);
+      launch(fwd_local<bf16_t, false>, grid, dim3(kRowTile), fwd_lds(), s, e0, e1, *L, (const bf16_t *)Qlow, nk,
+             (const BlockDesc *)W.desc, vin, W.t, (const State *)st, flags);
     } else if (!rform) {
-      hipLaunchKernelGGL((fwd_local<double, false>), grid, dim3(kRowTile), fwd_lds(), s, *L, A->Q,
-                         nk, W.desc, vin, W.t, st, flags);
+      launch(fwd_local<double, false>, grid, dim3(kRowTile), fwd_lds(), s, e0, e1, *L, (const double *)A->Q, nk,
+             (const BlockDesc *)W.desc, vin, W.t, (const State *)st, flags);
     } else {
-      hipLaunchKernelGGL(trsv_upper, dim3(L->J), dim3(kTriThreads), tri_lds(), s, *L, A->rank, A->R, vin,
-                         W.xs, st, flags);
-      hipLaunchKernelGGL((fwd_local<double, true>), grid, dim3(kRowTile), fwd_lds(), s, *L, A->M, A->kept,
-                         W.desc, W.xs, W.t, st, flags & F_CHECK_DONE);
+      launch(trsv_upper, dim3(L->J), dim3(kTriThreads), tri_lds(), s, e0, (hipEvent_t) nullptr, *L, A->rank,
+             (const double *)A->R, vin, W.xs, (const State *)st, flags);
+      launch(fwd_local<double, true>, grid, dim3(kRowTile), fwd_lds(), s, (hipEvent_t) nullptr, e1, *L,
+             (const double *)A->M, A->kept, (const BlockDesc *)W.desc, (const double *)W.xs, W.t, (const State *)st,
+             flags & F_CHECK_DONE);
     }
   }
-  void gather(hipStream_t s, const double *pcur, double *pnew, State *st, int mode) {
-    hipLaunchKernelGGL(fwd_gather, dim3(g_rows()), dim3(kVecThreads), 0, s, *L, W.t, h, pcur, pnew, W.ub,
-                       W.part, W.part2, st, mode);
+  void gather(hipStream_t s, const double *pcur, double *pnew, State *st, int mode, hipEvent_t e0 = nullptr,
+              hipEvent_t e1 = nullptr) {
+    launch(fwd_gather, dim3(g_rows()), dim3(kVecThreads), 0, s, e0, e1, *L, (const double *)W.t, h, pcur, pnew,
+           W.ub, W.part, W.part2, (const State *)st, mode);
   }
   // q = A^T u (- beta v in ITER mode), u = p / beta outside RESID mode; partials of ||q||^2.
   // p is the vector of the last gather (read from its block-row copy W.ub).
-  void adj(hipStream_t s, const double *pnew, const double *qcur, double *qnew, State *st, int mode) {
-    (void)pnew;
+  void adj(hipStream_t s, const double *qcur, double *qnew, State *st, int mode, hipEvent_t e0 = nullptr,
+           hipEvent_t e1 = nullptr) {
     const double *ubk = W.ub;
     int flags = 0;
     if (mode == ITER) flags = F_CHECK_DONE | F_DIV_BETA | F_COMBINE;
@@ -768,49 +789,48 @@ struct Launcher {
     double *pout = (mode == ITER && fused()) ? W.part3 : W.part;
     const dim3 grid(g_adj_x(), L->J);
     const int32_t *nk = nullptr;
+    const BlockDesc *dsc = W.desc;
+    const State *cst = st;
     if (!rform && dtype == RFM_F32) {
-      hipLaunchKernelGGL((adj_local<float, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
-                         (const float *)Qlow, nk, W.desc, ubk, qcur, qnew, pout, ct, st, flags);
+      launch(adj_local<float, false>, grid, dim3(kAdjThreads), adj_lds(), s, e0, e1, *L, (const float *)Qlow, nk,
+             dsc, ubk, qcur, qnew, pout, ct, cst, flags);
     } else if (!rform && dtype == RFM_BF16) {
-      hipLaunchKernelGGL((adj_local<bf16_t, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L,
-                         (const bf16_t *)Qlow, nk, W.desc, ubk, qcur, qnew, pout, ct, st, flags);
+      launch(adj_local<bf16_t, false>, grid, dim3(kAdjThreads), adj_lds(), s, e0, e1, *L, (const bf16_t *)Qlow,
+             nk, dsc, ubk, qcur, qnew, pout, ct, cst, flags);
     } else if (!rform) {
-      hipLaunchKernelGGL((adj_local<double, false>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->Q,
-                         nk, W.desc, ubk, qcur, qnew, pout, ct, st, flags);
+      launch(adj_local<double, false>, grid, dim3(kAdjThreads), adj_lds(), s, e0, e1, *L, (const double *)A->Q,
+             nk, dsc, ubk, qcur, qnew, pout, ct, cst, flags);
     } else {
-      hipLaunchKernelGGL((adj_local<double, true>), grid, dim3(kAdjThreads), adj_lds(), s, *L, A->M, A->kept,
-                         W.desc, ubk, qcur, W.zs, W.part, ct, st, flags & ~F_COMBINE);
-      hipLaunchKernelGGL(trsv_upper_t, dim3(L->J), dim3(kTriThreads), tri_lds(), s, *L, A->rank, A->R, W.zs,
-                         qcur, qnew, W.part, st, flags & (F_CHECK_DONE | F_COMBINE));
+      launch(adj_local<double, true>, grid, dim3(kAdjThreads), adj_lds(), s, e0, (hipEvent_t) nullptr, *L,
+             (const double *)A->M, A->kept, dsc, ubk, qcur, W.zs, W.part, ct, cst, flags & ~F_COMBINE);
+      launch(trsv_upper_t, dim3(L->J), dim3(kTriThreads), tri_lds(), s, (hipEvent_t) nullptr, e1, *L, A->rank,
+             (const double *)A->R, (const double *)W.zs, qcur, qnew, W.part, cst, flags & (F_CHECK_DONE | F_COMBINE));
     }
   }
-  void yw(hipStream_t s, const double *qnew, double *y, State *st, int mode) {
+  void yw(hipStream_t s, const double *qnew, double *y, State *st, int mode, hipEvent_t e0 = nullptr,
+          hipEvent_t e1 = nullptr) {
     // fused: alpha and the rotation from the adjoint partials (W.part3)
     const bool fz = (mode == ITER && fused());
-    hipLaunchKernelGGL(yw_update, dim3(g_cols()), dim3(kVecThreads), 0, s, L->ncols, qnew, W.w, y,
-                       W.part, st, mode, fz ? (const double *)W.part3 : nullptr, fz ? n_adj_part() : (int64_t)0);
+    launch(yw_update, dim3(g_cols()), dim3(kVecThreads), 0, s, e0, e1, (int64_t)L->ncols, qnew, W.w, y, W.part,
+           st, mode, fz ? (const double *)W.part3 : (const double *)nullptr, fz ? n_adj_part() : (int64_t)0);
   }
-  void reduce(hipStream_t s, int64_t n, State *st, int what) {
-    hipLaunchKernelGGL(reduce_step, dim3(1), dim3(kRedThreads), 0, s, W.part, n, W.part2, st, what);
+  void reduce(hipStream_t s, int64_t n, State *st, int what, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    launch(reduce_step, dim3(1), dim3(kRedThreads), 0, s, e0, e1, (const double *)W.part, n,
+           (const double *)W.part2, st, what);
   }
-  // ev (nullable): 6 events around the five stages of one iteration (the fused Q form has
-  // no separate alpha / rotation stage: ev[3] and ev[4] are recorded back to back)
+  // ev (nullable): 2 * kStages events, a start and an end per stage of one iteration, stamped
+  // by the stage's kernels (the fused Q form has no separate alpha / rotation stage)
   void iteration(hipStream_t s, int64_t i, double *y, hipEvent_t *ev) {
     const int a = (int)((i - 1) & 1), b = (int)(i & 1);
     const bool fz = fused();
-    if (ev) hipEventRecord(ev[0], s);
-    fwd(s, W.q[a], W.st, ITER);
-    if (ev) hipEventRecord(ev[1], s);
-    gather(s, W.p[a], W.p[b], W.st, ITER);
-    reduce(s, g_rows(), W.st, R_BETA);
-    if (ev) hipEventRecord(ev[2], s);
-    adj(s, W.p[b], W.q[a], W.q[b], W.st, ITER);
-    if (ev) hipEventRecord(ev[3], s);
-    if (!fz) reduce(s, n_adj_part(), W.st, R_ALPHA);
-    if (ev) hipEventRecord(ev[4], s);
-    yw(s, W.q[b], y, W.st, ITER);
-    reduce(s, g_cols(), W.st, fz ? R_YF : R_Y);
-    if (ev) hipEventRecord(ev[5], s);
+    auto E = [&](int k) { return ev ? ev[k] : (hipEvent_t) nullptr; };
+    fwd(s, W.q[a], W.st, ITER, E(0), E(1));
+    gather(s, W.p[a], W.p[b], W.st, ITER, E(2), nullptr);
+    reduce(s, g_rows(), W.st, R_BETA, nullptr, E(3));
+    adj(s, W.q[a], W.q[b], W.st, ITER, E(4), E(5));
+    if (!fz) reduce(s, n_adj_part(), W.st, R_ALPHA, E(6), E(7));
+    yw(s, W.q[b], y, W.st, ITER, E(8), nullptr);
+    reduce(s, g_cols(), W.st, fz ? R_YF : R_Y, nullptr, E(9));
   }
 };
 
@@ -884,7 +904,7 @@ rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, doub
     X.gather(st, nullptr, X.W.p[0], X.W.st, COPYH);
     X.reduce(st, X.g_rows(), X.W.st, R_BETA_INIT);
   }
-  X.adj(st, X.W.p[0], nullptr, X.W.q[0], X.W.st, INIT);
+  X.adj(st, nullptr, X.W.q[0], X.W.st, INIT);
   X.reduce(st, X.n_adj_part(), X.W.st, R_ALPHA_INIT);
   X.yw(st, X.W.q[0], y, X.W.st, INIT);
   X.reduce(st, X.g_cols(), X.W.st, R_Y_INIT);
@@ -901,7 +921,7 @@ rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, doub
   const bool graph = use_graph && batch > sampled;
   EventPool pool;
   Graph G;
-  if (times) RFM_HIP_TRY(pool.init((size_t)(kStages + 1) * sampled));
+  if (times) RFM_HIP_TRY(pool.init((size_t)(2 * kStages) * sampled));
   if (graph && !hs.done) {
     RFM_HIP_TRY(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
     RFM_HIP_TRY(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
@@ -914,7 +934,7 @@ rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, doub
   }
   while (!hs.done && i < maxit) {
     const int64_t first = i + 1;
-    for (int64_t b = 0; b < sampled; ++b) X.iteration(st, ++i, y, pool.ev.data() + (kStages + 1) * b);
+    for (int64_t b = 0; b < sampled; ++b) X.iteration(st, ++i, y, pool.ev.data() + 2 * kStages * b);
     if (graph) {
       RFM_HIP_TRY(hipGraphLaunch(G.ge, st));
       i += batch - sampled;
@@ -929,7 +949,7 @@ rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, doub
       for (int k = 0; k < kStages; ++k) {
         if (k == 3 && X.fused()) continue;  // no separate alpha / rotation launch
         float ms = 0.f;
-        const size_t e0 = (size_t)(kStages + 1) * b + k;
+        const size_t e0 = (size_t)(2 * kStages) * b + 2 * k;
         RFM_HIP_TRY(hipEventElapsedTime(&ms, pool.ev[e0], pool.ev[e0 + 1]));
         times->ms[k] += ms;
         times->launches[k] += 1;
@@ -946,7 +966,7 @@ rfm_status explicit_check(Launcher &X, const double *y, hipStream_t st, State *o
   X.fwd(st, y, X.W.st2, RESID);
   X.gather(st, nullptr, X.W.res, X.W.st2, RESID);
   X.reduce(st, X.g_rows(), X.W.st2, R_CHK_R);
-  X.adj(st, X.W.res, nullptr, X.W.z, X.W.st2, RESID);
+  X.adj(st, nullptr, X.W.z, X.W.st2, RESID);
   X.reduce(st, X.n_adj_part(), X.W.st2, R_CHK_AT);
   hipLaunchKernelGGL(sq_partials, dim3(X.g_cols()), dim3(kVecThreads), 0, st, X.L->ncols, y, X.W.part);
   X.reduce(st, X.g_cols(), X.W.st2, R_Y_INIT);
