@@ -65,6 +65,23 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return ((lane_read(v, 15) + lane_read(v, 31)) + lane_read(v, 47)) + lane_read(v, 63);
 }
 
+// Two wave sums at once (the same fixed order as wave_sum_dpp for each), interleaved so
+// that the two chains hide each other's latency.
+__device__ __forceinline__ void wave_sum2_dpp(double &a, double &b) {
+  a += dpp_row_shr<0x111>(a);
+  b += dpp_row_shr<0x111>(b);
+  a += dpp_row_shr<0x112>(a);
+  b += dpp_row_shr<0x112>(b);
+  a += dpp_row_shr<0x114>(a);
+  b += dpp_row_shr<0x114>(b);
+  a += dpp_row_shr<0x118>(a);
+  b += dpp_row_shr<0x118>(b);
+  const double a0 = lane_read(a, 15), b0 = lane_read(b, 15), a1 = lane_read(a, 31), b1 = lane_read(b, 31);
+  const double a2 = lane_read(a, 47), b2 = lane_read(b, 47), a3 = lane_read(a, 63), b3 = lane_read(b, 63);
+  a = ((a0 + a1) + a2) + a3;
+  b = ((b0 + b1) + b2) + b3;
+}
+
 // Sum over a workgroup of nthreads (multiple of 64) in a fixed order; result valid
 // in every thread.  scratch holds at least nthreads/64 doubles of LDS.
 __device__ __forceinline__ double block_sum(double v, double *scratch) {

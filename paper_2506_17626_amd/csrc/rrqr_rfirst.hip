@@ -61,8 +61,7 @@ __device__ __forceinline__ double reflect(double (&x)[TT], int r0, int s, int hi
     if (row == s) alpha = x[t];
     else if (row > s && row < hi) sig2 += x[t] * x[t];
   }
-  alpha = wave_sum_dpp(alpha);  // one non-zero term
-  sig2 = wave_sum_dpp(sig2);
+  wave_sum2_dpp(alpha, sig2);  // alpha: one non-zero term
   if (sig2 == 0.0) {
 #pragma unroll
     for (int t = 0; t < TT; ++t) {
@@ -73,7 +72,7 @@ __device__ __forceinline__ double reflect(double (&x)[TT], int r0, int s, int hi
   }
   const double nrm = sqrt(alpha * alpha + sig2);
   const double beta = (alpha >= 0.0) ? -nrm : nrm;
-  const double den = alpha - beta;
+  const double rden = 1.0 / (alpha - beta);
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
     const int row = r0 + lane + kWave * t;
@@ -81,10 +80,47 @@ __device__ __forceinline__ double reflect(double (&x)[TT], int r0, int s, int hi
       x[t] = beta;
       vdst[0] = 1.0;
     } else if (row > s && row < hi) {
-      const double vi = x[t] / den;
+      const double vi = x[t] * rden;
       x[t] = vi;
       vdst[row - s] = vi;
     }
+  }
+  return (beta - alpha) / beta;
+}
+
+// As reflect, branch-free, for a column held as rows r0 + lane + 64 t (t < TT) whose
+// reflector row vrow has room for all 64 TT of them: every lane stores all TT entries of
+// v by row - r0 (zero above the pivot row s and from hi on), so no conditional stores.
+template <int TT>
+__device__ __forceinline__ double reflect_rows(double (&x)[TT], int r0, int s, int hi, double *vrow) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double alpha = 0.0, sig2 = 0.0;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    const int row = r0 + lane + kWave * t;
+    alpha += (row == s) ? x[t] : 0.0;
+    const double xb = (row > s && row < hi) ? x[t] : 0.0;
+    sig2 = fma(xb, xb, sig2);
+  }
+  wave_sum2_dpp(alpha, sig2);  // alpha: one non-zero term
+  if (sig2 == 0.0) {
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      const int row = r0 + lane + kWave * t;
+      vrow[lane + kWave * t] = (row == s) ? 1.0 : 0.0;
+    }
+    return 0.0;
+  }
+  const double nrm = sqrt(alpha * alpha + sig2);
+  const double beta = (alpha >= 0.0) ? -nrm : nrm;
+  const double rden = 1.0 / (alpha - beta);
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    const int row = r0 + lane + kWave * t;
+    const bool below = row > s && row < hi;
+    const double vi = below ? x[t] * rden : 0.0;
+    vrow[lane + kWave * t] = (row == s) ? 1.0 : vi;
+    x[t] = (row == s) ? beta : (below ? vi : x[t]);
   }
   return (beta - alpha) / beta;
 }
@@ -115,6 +151,28 @@ __device__ __forceinline__ void apply_refl1(double (&x)[TT], const double (&vr)[
   f = wave_sum_dpp(f);
 #pragma unroll
   for (int t = 0; t < TT; ++t) x[t] -= th * (vr[t] * f);
+}
+
+// apply_refl1 on two columns of one wave with one interleaved reduction; a column whose
+// flag is off is left as it is.
+template <int TT>
+__device__ __forceinline__ void apply_refl1x2(double (&x)[TT], double (&y)[TT], const double (&vr)[TT], double th,
+                                              bool onx, bool ony) {
+  double f = 0.0, g = 0.0;
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    f += vr[t] * x[t];
+    g += vr[t] * y[t];
+  }
+  wave_sum2_dpp(f, g);
+  if (onx) {
+#pragma unroll
+    for (int t = 0; t < TT; ++t) x[t] -= th * (vr[t] * f);
+  }
+  if (ony) {
+#pragma unroll
+    for (int t = 0; t < TT; ++t) y[t] -= th * (vr[t] * g);
+  }
 }
 
 // As apply_refl, with v read from LDS (row lane + 64 t at v[lane + 64 t], rows >= nv zero)
@@ -166,10 +224,17 @@ __device__ __forceinline__ double row16_sum(double v) {
 // th; a 16-lane reduction per reflector serves the four columns of a wave at once.
 template <int R16>
 __device__ __forceinline__ void apply_refl16(double (&x)[R16], const double *v, double th) {
+  static_assert(R16 % 4 == 0, "four interleaved partial dot products");
   const int li = threadIdx.x & 15;
-  double f = 0.0;
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0;
 #pragma unroll
-  for (int t = 0; t < R16; ++t) f = fma(v[li + 16 * t], x[t], f);
+  for (int t = 0; t < R16; t += 4) {
+    f0 = fma(v[li + 16 * t], x[t], f0);
+    f1 = fma(v[li + 16 * (t + 1)], x[t + 1], f1);
+    f2 = fma(v[li + 16 * (t + 2)], x[t + 2], f2);
+    f3 = fma(v[li + 16 * (t + 3)], x[t + 3], f3);
+  }
+  double f = (f0 + f1) + (f2 + f3);
   f = row16_sum(f);
   const double g = -th * f;
 #pragma unroll
@@ -194,10 +259,11 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
     double *Vp = lds + L.max_cols;
     constexpr bool Q16 = T <= 12;     // trailing update with one column per 16 lanes
     const int ldv = Q16 ? 64 * T : m;  // reflector rows zero-padded to 64 T in that case
-    for (int64_t e = tid; e < (int64_t)m * n; e += NT) A[e] = Mj[e];
-    __syncthreads();
+    // the first panel reads M_j itself and every column of the slot is stored in it, so M_j
+    // is not copied separately (m = 0 or n = 0: nothing to store)
     for (int p = 0; p < nr; p += nb) {
       const int b = min(nb, nr - p);
+      const double *__restrict__ src = (p == 0) ? Mj : A;
       // the panel's columns in registers: column p + w + NW u
       double pc[NPC][T];
 #pragma unroll
@@ -206,18 +272,24 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
 #pragma unroll
         for (int t = 0; t < T; ++t) {
           const int row = p + lane + kWave * t;
-          pc[u][t] = (k < p + b && row < m) ? A[(int64_t)k * m + row] : 0.0;
+          pc[u][t] = (k < p + b && row < m) ? src[(int64_t)k * m + row] : 0.0;
         }
       }
       for (int i = 0; i < b; ++i) {
         const int s = p + i;
         if (w == i % NW) {
           double *vrow = Vp + (int64_t)i * ldv;
-          for (int rr = lane; rr < i; rr += kWave) vrow[rr] = 0.0;
-          for (int rr = m - p + lane; rr < ldv; rr += kWave) vrow[rr] = 0.0;
           double th;
-          if (NPC == 1 || i < NW) th = reflect<T>(pc[0], p, s, m, vrow + i);
-          else th = reflect<T>(pc[NPC - 1], p, s, m, vrow + i);
+          if constexpr (Q16) {
+            // the padded row (64 T entries from row p) is written whole
+            if (NPC == 1 || i < NW) th = reflect_rows<T>(pc[0], p, s, m, vrow);
+            else th = reflect_rows<T>(pc[NPC - 1], p, s, m, vrow);
+          } else {
+            for (int rr = lane; rr < i; rr += kWave) vrow[rr] = 0.0;
+            for (int rr = m - p + lane; rr < ldv; rr += kWave) vrow[rr] = 0.0;
+            if (NPC == 1 || i < NW) th = reflect<T>(pc[0], p, s, m, vrow + i);
+            else th = reflect<T>(pc[NPC - 1], p, s, m, vrow + i);
+          }
           if (lane == 0) taus[s] = th;
         }
         __syncthreads();
@@ -230,10 +302,18 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
 #pragma unroll
           for (int t = 0; t < T; ++t) {
             const int rr = lane + kWave * t;
-            vr[t] = (p + rr < m) ? Vp[(int64_t)i * ldv + rr] : 0.0;
+            // Q16: rows of the padded reflector are zero from m - p on
+            vr[t] = (Q16 || p + rr < m) ? Vp[(int64_t)i * ldv + rr] : 0.0;
           }
-          if (p + w > s && p + w < p + b) apply_refl1<T>(pc[0], vr, th);
-          if (NPC > 1 && p + w + NW > s && p + w + NW < p + b) apply_refl1<T>(pc[NPC - 1], vr, th);
+          const bool on0 = p + w > s && p + w < p + b;
+          if constexpr (NPC > 1) {
+            const bool on1 = p + w + NW > s && p + w + NW < p + b;
+            if (on0 && on1) apply_refl1x2<T>(pc[0], pc[NPC - 1], vr, th, true, true);
+            else if (on0) apply_refl1<T>(pc[0], vr, th);
+            else if (on1) apply_refl1<T>(pc[NPC - 1], vr, th);
+          } else if (on0) {
+            apply_refl1<T>(pc[0], vr, th);
+          }
         }
       }
 #pragma unroll
@@ -257,7 +337,7 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
 #pragma unroll
           for (int t = 0; t < R16; ++t) {
             const int row = p + li + 16 * t;
-            x[t] = (k < n && row < m) ? A[(int64_t)k * m + row] : 0.0;
+            x[t] = (k < n && row < m) ? src[(int64_t)k * m + row] : 0.0;
           }
           for (int i = 0; i < b; ++i) apply_refl16<R16>(x, Vp + (int64_t)i * ldv, taus[p + i]);
           if (k < n) {
@@ -277,7 +357,7 @@ __global__ __launch_bounds__(NT) void rf_qr(rfm_layout L, const double *__restri
 #pragma unroll
           for (int t = 0; t < T; ++t) {
             const int row = p + lane + kWave * t;
-            x[g][t] = (k < n && row < m) ? A[(int64_t)k * m + row] : 0.0;
+            x[g][t] = (k < n && row < m) ? src[(int64_t)k * m + row] : 0.0;
           }
         }
         for (int i = 0; i < b; ++i) {
