@@ -92,7 +92,8 @@ __device__ __forceinline__ double reflect(double (&x)[TT], int r0, int s, int hi
 // reflector row vrow has room for all 64 TT of them: every lane stores all TT entries of
 // v by row - r0 (zero above the pivot row s and from hi on), so no conditional stores.
 template <int TT>
-__device__ __forceinline__ double reflect_rows(double (&x)[TT], int r0, int s, int hi, double *vrow) {
+__device__ __forceinline__ double reflect_rows(double (&x)[TT], int r0, int s, int hi, double *vrow,
+                                               double *diag = nullptr) {
   const int lane = threadIdx.x & (kWave - 1);
   double alpha = 0.0, sig2 = 0.0;
 #pragma unroll
@@ -109,10 +110,12 @@ __device__ __forceinline__ double reflect_rows(double (&x)[TT], int r0, int s, i
       const int row = r0 + lane + kWave * t;
       vrow[lane + kWave * t] = (row == s) ? 1.0 : 0.0;
     }
+    if (diag) *diag = alpha;
     return 0.0;
   }
   const double nrm = sqrt(alpha * alpha + sig2);
   const double beta = (alpha >= 0.0) ? -nrm : nrm;
+  if (diag) *diag = beta;
   const double rden = 1.0 / (alpha - beta);
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
@@ -635,15 +638,10 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
       double x[TR];
 #pragma unroll
       for (int t = 0; t < TR; ++t) x[t] = pcol[lane + kWave * t];
-      const double th = reflect<TR>(x, 0, s, nr, vabs + s);
-      double dg = 0.0;
-#pragma unroll
-      for (int t = 0; t < TR; ++t) {
-        const int row = lane + kWave * t;
-        if (row == s) dg = x[t];
-        if (row < s || row >= nr) vabs[row] = 0.0;
-      }
-      dg = wave_sum_dpp(dg);
+      // the whole row range 0..64 TR - 1 of vabs is written (zero outside [s, nr)); dg is
+      // the new diagonal entry
+      double dg;
+      const double th = reflect_rows<TR>(x, 0, s, nr, vabs, &dg);
       if (lane == 0) {
         t1[s] = th;
         ds[s] = (dg < 0.0) ? -1.0 : 1.0;
