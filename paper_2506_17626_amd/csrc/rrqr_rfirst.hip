@@ -929,12 +929,13 @@ __global__ __launch_bounds__(NT) void rf_formq0(rfm_layout L, const int32_t *__r
 // slice, so the rows it overwrites have been read.
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-template <int CP>
+template <int CP, int RA>
 __global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__restrict__ rank,
                                               double *__restrict__ Q, const double *__restrict__ W2,
                                               const double *__restrict__ dsgn, const int32_t *__restrict__ order) {
-  constexpr int RT = 16384 / CP, KC = 16;
-  constexpr int RT16 = RT / 16, WR = RT16 / 2;  // row-tile pairs; waves laid out WR x (NW / WR)
+  // row tiles of RT rows; each wave holds RA x 4 output tiles of 16 x 16, the waves laid out
+  // WR x (NW / WR); Z (Q1 D) is read once per row tile, so taller tiles read it fewer times
+  constexpr int WR = NW * 64 / CP, RT = 16 * RA * WR, KC = 16;
   __shared__ double As[KC][RT];
   __shared__ double Zs[KC][CP];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
@@ -948,9 +949,9 @@ __global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__res
   const double *__restrict__ Z = W2 + B.rsq;
   constexpr int NA = KC * RT / NT, NZ = KC * CP / NT;
   for (int i0 = 0; i0 < m; i0 += RT) {
-    d4_t acc[2][4];
+    d4_t acc[RA][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = d4_t{0.0, 0.0, 0.0, 0.0};
     double pa[NA], pz[NZ];
@@ -982,13 +983,13 @@ __global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__res
       if (k0 + KC < nr) fetch(k0 + KC);
 #pragma unroll
       for (int kq = 0; kq < KC; kq += 4) {
-        double av[2], bv[4];
+        double av[RA], bv[4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = As[kq + lk][(2 * wr + a) * 16 + li];
+        for (int a = 0; a < RA; ++a) av[a] = As[kq + lk][(RA * wr + a) * 16 + li];
 #pragma unroll
         for (int b = 0; b < 4; ++b) bv[b] = Zs[kq + lk][(4 * wc + b) * 16 + li];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
           for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
@@ -1000,10 +1001,10 @@ __global__ __launch_bounds__(NT) void rf_gemm(rfm_layout L, const int32_t *__res
       if (q < r) {
         const double sg = dsgn[B.f0 + q];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int row = i0 + (2 * wr + a) * 16 + lk + 4 * v;
+            const int row = i0 + (RA * wr + a) * 16 + lk + 4 * v;
             if (row < m) A[(int64_t)q * m + row] = sg * acc[a][b][v];
           }
       }
@@ -1157,9 +1158,9 @@ rfm_status rrqr_rfirst(const RfirstArgs &a) {
   if (s != RFM_OK) return s;
   const dim3 grid((unsigned)L->J);
   if (nr_max <= 256)
-    hipLaunchKernelGGL(rf_gemm<256>, grid, dim3(NT), 0, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
+    hipLaunchKernelGGL((rf_gemm<256, 3>), grid, dim3(NT), 0, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
   else
-    hipLaunchKernelGGL(rf_gemm<512>, grid, dim3(NT), 0, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
+    hipLaunchKernelGGL((rf_gemm<512, 2>), grid, dim3(NT), 0, a.st, *L, a.rank, a.Q, W.W2, W.dsgn, a.order);
   RFM_LAUNCH_CHECK();
   return RFM_OK;
 }
