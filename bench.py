@@ -103,6 +103,76 @@ def cpu_baseline(inst, tau, nblocks):
                       f"{inst.J} blocks, one thread, {dt:.1f} s"}
 
 
+def learned_ceiling(model, ts, Yc):
+    """The network's reach (a bound that follows from its shape): every start it can produce lies
+    in the affine space {diag(sd) (W3^T z + b3) + mean}, of dimension at most its last hidden width.
+    Returns the relative error of the best start in that space for each held-out solution, and the
+    number of singular values of the training targets above 1e-2 and 1e-3 of the largest."""
+    import numpy as np
+
+    W3 = model.P["W3"].double().cpu().numpy()            # [hidden, ncols]
+    b3 = model.P["b3"].double().cpu().numpy()
+    sd = model.sd.double().cpu().numpy()
+    mu = model.mean.double().cpu().numpy()
+    A = (W3 * sd[None, :]).T                              # [ncols, hidden]
+    Y = Yc.double().cpu().numpy()
+    Z = Y - (b3 * sd + mu)[:, None]
+    Qa, _ = np.linalg.qr(A, mode="reduced")
+    res = Z - Qa @ (Qa.T @ Z)
+    rel = np.linalg.norm(res, axis=0) / np.linalg.norm(Y, axis=0)
+    T = ts.T.double().cpu().numpy()
+    ev = np.sqrt(np.clip(np.linalg.eigvalsh(T @ T.T), 0.0, None))[::-1]
+    return rel, int((ev > 1e-2 * ev[0]).sum()), int((ev > 1e-3 * ev[0]).sum())
+
+
+def superposition_reference(args, plan, fact, inst, prob, test, Ht, Yc, note):
+    """The exact linear map from the family parameters to the solution: each member is
+    sum_k a_k Y[m_k, n_k] over mode solutions Y (the system matrix is fixed, the right-hand side is
+    linear in a).  Solves the distinct modes of the held-out members to the rule, takes the
+    superposition as the start of each member and solves warm (the reference a learned start is
+    measured against)."""
+    import numpy as np
+    import torch
+
+    from paper_2506_17626_amd import learned, rfm
+
+    nm = test.shape[1] // 3
+    modes = sorted({(int(r[nm + q]), int(r[2 * nm + q])) for r in test for q in range(nm)})
+    idx = {mk: q for q, mk in enumerate(modes)}
+    mp = np.zeros((len(modes), 3 * nm))
+    mp[:, 0] = 1.0
+    mp[:, nm:] = 1.0
+    for q, (m, k) in enumerate(modes):
+        mp[q, nm], mp[q, 2 * nm] = m, k
+    t0 = time.perf_counter()
+    Ym, mode_iters = [], []
+    for g0 in range(0, len(modes), 64):
+        Hm = learned.family_rhs(inst, prob, mp[g0:g0 + 64])
+        Yg, itg, _ = rfm.rfm_lsqr_multi(plan, fact, Hm, atol=args.tol, btol=args.tol, maxit=args.maxit)
+        Ym.append(Yg.cpu().numpy())
+        mode_iters += list(itg)
+        note(f"mode solves {min(g0 + 64, len(modes))}/{len(modes)}")
+    Ym = np.concatenate(Ym, axis=1)
+    C = np.zeros((len(modes), len(test)))
+    for b, r in enumerate(test):
+        for q in range(nm):
+            C[idx[(int(r[nm + q]), int(r[2 * nm + q]))], b] += r[q]
+    Y0 = torch.from_numpy(np.ascontiguousarray(Ym @ C)).to(Yc.device)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rej = np.zeros(len(test), dtype=np.int32)
+    Ys, isup, ssup = rfm.rfm_lsqr_multi(plan, fact, Ht, Y0=Y0, atol=args.tol, btol=args.tol, maxit=args.maxit,
+                                        rejected=rej)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    err = (torch.linalg.norm(Y0 - Yc, dim=0) / torch.linalg.norm(Yc, dim=0)).cpu().numpy()
+    return {"modes": len(modes), "mode_solve_s": t1 - t0, "mode_iters_mean": float(np.mean(mode_iters)),
+            "start_rel_err_mean": float(np.mean(err)), "start_rel_err_max": float(np.max(err)),
+            "starts_rejected": int(rej.sum()), "warm_iters_mean": float(np.mean(isup)),
+            "warm_iters": isup.tolist(), "warm_stops": np.bincount(ssup, minlength=5).tolist(),
+            "warm_solve_s": t2 - t1}
+
+
 def learned_study(args):
     """Learned warm start on the parametric Poisson family (2D geometry, 16x16 subdomains, 256
     features): training solves by multi-RHS LSQR (capped), perceptron trained on the device,
@@ -149,6 +219,12 @@ def learned_study(args):
     t3 = time.perf_counter()
     start_err = (torch.linalg.norm(Y0 - Yc, dim=0) / torch.linalg.norm(Yc, dim=0)).cpu().numpy()
     sol_diff = (torch.linalg.norm(Yw - Yc, dim=0) / torch.linalg.norm(Yc, dim=0)).cpu().numpy()
+    best, rank2, rank3 = learned_ceiling(model, ts, Yc)
+    note(f"network reach: best start in its output space {np.median(best):.3f} (median relative error); "
+         f"training targets: {rank2} / {rank3} singular values above 1e-2 / 1e-3 of the largest")
+    sup = superposition_reference(args, plan, fact, inst, prob, test, Ht, Yc, note)
+    note(f"superposition starts: error {sup['start_rel_err_mean']:.2e}, warm {sup['warm_iters_mean']:.0f} "
+         f"iterations against cold {np.mean(ic):.0f}")
     singles = []
     for b in range(min(args.n_single, len(test))):
         hb = Ht[:, b].contiguous()
@@ -176,6 +252,10 @@ def learned_study(args):
         "heldout_stops_cold": np.bincount(sc, minlength=5).tolist(),
         "heldout_stops_warm": np.bincount(sw, minlength=5).tolist(), "heldout_starts_rejected": int(rej.sum()),
         "start_rel_err_mean": float(np.mean(start_err)), "warm_vs_cold_solution_rel_diff_max": float(sol_diff.max()),
+        "network_reach": {"best_start_rel_err_median": float(np.median(best)),
+                          "best_start_rel_err_min": float(np.min(best)), "hidden": int(model.P["W3"].shape[0]),
+                          "target_sv_above_1e-2": rank2, "target_sv_above_1e-3": rank3},
+        "superposition_reference": sup,
         "single_solves": singles,
     }
     print(json.dumps(out), flush=True)
