@@ -422,6 +422,41 @@ def test_precision_form_warm_start_guard(rfm):
     assert ig.warm_rejected == 0 and ig.stop in (1, 2, 4) and ig.iters < ic.iters
 
 
+def test_precision_form_default_is_one_narrow_solve_to_the_rule(rfm):
+    """With the default options the precision form is one LSQR solve on the FP32 copy to the
+    caller's rule, then the binary64 test (and finish where it fails): the binary64
+    least-squares solution, in one outer step.  A start near the solution enters the narrow solve
+    itself (its rule relative to ||h|| and ||y||), so that solve needs fewer iterations than
+    from zero; a correction solve on the small residual, with its rule relative to ||r||, would
+    need more."""
+    inst = I.tiny("heat3d")
+    print("[mixed default] heat3d tau=1e-10", flush=True)
+    rows, blocks, h, facts, plan, fact = _shared_fact(rfm, inst, 1e-10)
+    fact["Qlow"] = rfm.rfm_pack_q(plan, fact, rfm.F32)
+    A = olsqr.QForm(inst.N, rows, [f.Q for f in facts])
+    D = np.stack([A.matvec(e) for e in np.eye(A.n)], axis=1)
+    ystar = np.linalg.lstsq(D, h, rcond=None)[0]
+    kappa = np.linalg.cond(D)
+    kw = dict(atol=1e-11, btol=1e-11, maxit=50000, inner_dtype=rfm.F32)
+    y, info = rfm.rfm_lsqr_solve(plan, fact, _dev(h), **kw)
+    torch.cuda.synchronize()
+    ypad = H.pack_y(inst.feat_off, facts, ystar)
+    rel = np.linalg.norm(y.cpu().numpy() - ypad) / np.linalg.norm(ypad)
+    print(f"  outer {info.outer} iters {info.iters} (finish {info.polish}) stop {info.stop} rel {rel:.2e}",
+          flush=True)
+    assert info.outer == 1 and info.stop in (1, 2, 4)
+    assert rel <= 1e-9 * kappa
+    rng = np.random.default_rng(5)
+    y0 = H.pack_y(inst.feat_off, facts, ystar * (1.0 + 1e-6 * rng.standard_normal(ystar.shape)))
+    yw, iw = rfm.rfm_lsqr_solve(plan, fact, _dev(h), y0=_dev(y0), **kw)
+    torch.cuda.synchronize()
+    relw = np.linalg.norm(yw.cpu().numpy() - ypad) / np.linalg.norm(ypad)
+    print(f"  warm: iters {iw.iters} (finish {iw.polish}) rejected {iw.warm_rejected} rel {relw:.2e}", flush=True)
+    assert iw.warm_rejected == 0 and iw.stop in (1, 2, 4)
+    assert relw <= 1e-8 * kappa
+    assert iw.iters - iw.polish < info.iters - info.polish
+
+
 def test_batching_form_results_independent_of_order_and_launch_shape(rfm):
     """Within each factorisation the results are bitwise independent of the block order and
     the launch shape: the R-first form in cost order, and the direct form with the persistent

@@ -86,3 +86,34 @@ def test_refinement_first_step_error_follows_kappa_u_low():
     y2, info = forms.refine(A, Al, h, atol=1e-12, btol=1e-12, inner_tol=1e-6)
     assert info.polish_iters > 0
     assert np.linalg.norm(y2 - ystar) <= 1e-9 * kappa * np.linalg.norm(ystar)
+
+
+def test_refinement_one_narrow_solve_to_the_rule_then_binary64_check():
+    """The precision form's default: one narrow LSQR solve to the caller's own tolerance, then the
+    binary64 test and, where it fails, the binary64 finish; the result is the binary64
+    least-squares solution."""
+    inst, rows, facts, A, h = _system("heat3d", 1e-10)
+    Al = forms.NarrowQForm(inst.N, rows, [f.Q for f in facts], "f32")
+    ystar, kappa = _dense_ls(A, h)
+    y, info = forms.refine(A, Al, h, atol=1e-12, btol=1e-12, inner_tol=1e-12, max_outer=1)
+    assert info.outer == 1 and info.stop in (1, 2, 4)
+    assert np.linalg.norm(y - ystar) <= 1e-9 * kappa * np.linalg.norm(ystar)
+    # from y = 0 the first narrow step is plain LSQR on h with the narrow operator
+    yl, il = lsqr.lsqr(Al, h, atol=1e-12, btol=1e-12, maxit=100000, anorm=np.sqrt(A.n))
+    assert info.inner_iters == il.iters
+
+
+def test_refinement_warm_first_step_starts_from_the_given_coefficients():
+    """A warm start enters the first narrow solve itself (LSQR on h from y0, its rule relative to
+    ||h|| and ||y||): a start near the solution needs far fewer narrow iterations than y0 = 0."""
+    inst, rows, facts, A, h = _system("heat3d", 1e-10)
+    Al = forms.NarrowQForm(inst.N, rows, [f.Q for f in facts], "f32")
+    ystar, kappa = _dense_ls(A, h)
+    kw = dict(atol=1e-10, btol=1e-10, inner_tol=1e-10, max_outer=1)
+    _, cold = forms.refine(A, Al, h, **kw)
+    rng = np.random.default_rng(3)
+    y0 = ystar * (1.0 + 1e-6 * rng.standard_normal(A.n))
+    y, warm = forms.refine(A, Al, h, y0=y0, **kw)
+    assert warm.stop in (1, 2, 4)
+    assert np.linalg.norm(y - ystar) <= 1e-8 * kappa * np.linalg.norm(ystar)
+    assert warm.inner_iters + warm.polish_iters < 0.5 * (cold.inner_iters + cold.polish_iters)
