@@ -274,7 +274,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-blocks", type=int, default=64)
+    ap.add_argument("--cpu-blocks", type=int, default=192)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (a device copy of known "
                          "size, used to calibrate the HBM byte counters of a profiler run)")
