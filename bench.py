@@ -103,6 +103,64 @@ def cpu_baseline(inst, tau, nblocks):
                       f"{inst.J} blocks, one thread, {dt:.1f} s"}
 
 
+def conditioning_study(args):
+    """Filter drop fraction and the condition of the preconditioned operator across tau (the
+    columns of the paper's tables).  For each workload and tau: the filter, then k steps of the
+    solver's Golub-Kahan bidiagonalisation on the workload's right-hand side (LSQR with the stop
+    rule off, recording alpha_i, beta_i); sigma_max(B_k) / sigma_min(B_k) is a lower bound of
+    kappa(A_hat) that grows with k (reported at k/4, k/2, k)."""
+    import torch
+
+    from paper_2506_17626_amd import instances as I
+    from paper_2506_17626_amd import rfm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    k = args.cond_steps
+    out = {"study": "conditioning", "steps": k, "taus": [], "workloads": {}}
+    taus = [1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12]
+    out["taus"] = taus
+    for name in args.cond_workloads.split(","):
+        inst = I.workload(name, seed=args.seed)
+        plan = rfm.plan_instance(inst)
+        prob = rfm.problem_tensors(inst)
+        M, h = rfm.rfm_assemble(plan, prob)
+        rows = []
+        for tau in taus:
+            fact = rfm.rfm_rrqr_filter(plan, M, tau)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fact = rfm.rfm_rrqr_filter(plan, M, tau, out=fact)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            kept = int(fact["rank"].sum())
+            bd = torch.zeros(2 * k + 2, dtype=torch.float64, device=dev)
+            _, info = rfm.rfm_lsqr_solve(plan, fact, h, atol=0.0, btol=0.0, maxit=k, check_every=64,
+                                         use_graph=1, bidiag=bd)
+            torch.cuda.synchronize()
+            g = bd.cpu().numpy()
+            ke = int(info.iters)  # steps taken (a breakdown ends the process early)
+            est = {}
+            for kk in sorted({max(1, ke // 4), max(1, ke // 2), ke}):
+                B = np.zeros((kk + 1, kk))
+                B[np.arange(kk), np.arange(kk)] = g[0:2 * kk:2]
+                B[np.arange(1, kk + 1), np.arange(kk)] = g[3:2 * kk + 2:2]
+                sv = np.linalg.svd(B, compute_uv=False)
+                est[kk] = (float(sv[0]), float(sv[-1]))
+            row = {"tau": tau, "kept": kept, "columns": int(sum(np.diff(plan.host["feat_off"]))),
+                   "drop_pct": 100.0 * (1 - kept / max(1, int(sum(np.diff(plan.host["feat_off"]))))),
+                   "filter_ms": 1e3 * (t1 - t0),
+                   "steps": ke, "stop": int(info.stop), "sigma_max": est[ke][0], "sigma_min_est": est[ke][1],
+                   "kappa_lower_bound": {str(kk): v[0] / v[1] for kk, v in est.items()}}
+            rows.append(row)
+            print(f"[conditioning] {name} tau={tau:g}: dropped {row['drop_pct']:.1f} %, kappa(A_hat) >= "
+                  f"{row['kappa_lower_bound'][str(ke)]:.3e} after {ke} steps", file=sys.stderr, flush=True)
+        out["workloads"][name] = rows
+        del M
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def learned_ceiling(model, ts, Yc):
     """The network's reach (a bound that follows from its shape): every start it can produce lies
     in the affine space {diag(sd) (W3^T z + b3) + mean}, of dimension at most its last hidden width.
@@ -278,6 +336,10 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size once (a device copy of known "
                          "size, used to calibrate the HBM byte counters of a profiler run)")
+    ap.add_argument("--conditioning", action="store_true",
+                    help="filter drop fraction and condition estimates of the preconditioned operator across tau")
+    ap.add_argument("--cond-steps", type=int, default=1000)
+    ap.add_argument("--cond-workloads", default="poisson1d,poisson2d,heat3d,helmholtz2d_uneven")
     ap.add_argument("--learned-study", action="store_true",
                     help="run the learned warm-start study on the parametric family instead of the bench")
     ap.add_argument("--n-train", type=int, default=1024)
@@ -286,6 +348,9 @@ def main():
     ap.add_argument("--train-iters", type=int, default=4000)
     ap.add_argument("--epochs", type=int, default=200)
     args = ap.parse_args()
+    if args.conditioning:
+        conditioning_study(args)
+        return
     if args.learned_study:
         learned_study(args)
         return

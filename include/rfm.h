@@ -255,6 +255,13 @@ typedef struct {
   double inner_tol;       /* precision form: atol = btol of the inner solves, in (0, 1) */
   int32_t adj_tile;       /* columns per workgroup of the adjoint block products (multiple of
                              16; 0 = default, see rfm_tuning) */
+  double *bidiag;         /* device, nullable, [2 * maxit + 2]: the Golub-Kahan bidiagonalisation
+                             A V_k = U_{k+1} B_k the solve runs on (plain solves only): entries
+                             (alpha_1, beta_1) first, then after iteration i (alpha_{i+1},
+                             beta_{i+1}) at [2 i], [2 i + 1]; B_k is lower bidiagonal with
+                             alpha_1..alpha_k on its diagonal and beta_2..beta_{k+1} below it, and
+                             its extreme singular values bound those of A from inside (entries past
+                             the last iteration untouched) */
 } rfm_lsqr_opts;
 
 typedef struct {

@@ -46,6 +46,7 @@ struct State {
   int64_t iter, maxit;
   int32_t done, stop;
   double *history;         // nullable device [2 * maxit]: (rnorm, artnorm) estimates
+  double *bidiag;          // nullable device [2 * maxit + 2]: (alpha_i, beta_i), i = 1..
 };
 
 enum Mode : int { ITER = 0, INIT = 1, RESID = 2, COPYH = 3 };
@@ -536,6 +537,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_step(const double *part, i
       st->beta = bn;
       st->rhobar = an;
       st->phibar = bn;
+      if (st->bidiag) {
+        st->bidiag[0] = an;
+        st->bidiag[1] = bn;
+      }
       st->rnorm = bn;
       st->artnorm = an * bn;
       st->iter = 0;
@@ -570,6 +575,10 @@ __global__ __launch_bounds__(kRedThreads) void reduce_step(const double *part, i
       if (st->history && st->iter <= st->maxit) {
         st->history[2 * (st->iter - 1)] = st->rnorm;
         st->history[2 * (st->iter - 1) + 1] = st->artnorm;
+      }
+      if (st->bidiag && st->iter <= st->maxit) {  // alpha_{i+1}, beta_{i+1} of iteration i
+        st->bidiag[2 * st->iter] = st->alpha;
+        st->bidiag[2 * st->iter + 1] = st->beta;
       }
       int stop = 0;
       if (st->beta == 0.0 || st->alpha == 0.0) stop = 4;
@@ -868,7 +877,8 @@ struct Graph {
 // (the cold start stays the fallback); *rejected (nullable) reports it.
 rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, double atol, double btol,
                     int64_t maxit, int check_every, bool use_graph, rfm_kernel_times *times,
-                    double *history, hipStream_t st, State *out, int32_t *rejected = nullptr) {
+                    double *history, hipStream_t st, State *out, int32_t *rejected = nullptr,
+                    double *bidiag = nullptr) {
   const rfm_layout *L = X.L;
   State hs{};
   hs.anorm = anorm;
@@ -876,6 +886,7 @@ rfm_status run_lsqr(Launcher &X, double anorm, const double *y0, double *y, doub
   hs.btol = btol;
   hs.maxit = maxit;
   hs.history = history;
+  hs.bidiag = bidiag;
   RFM_HIP_TRY(hipMemcpyAsync(X.W.st, &hs, sizeof(State), hipMemcpyHostToDevice, st));
   for (double *b : {X.W.q[0], X.W.q[1], X.W.w})
     hipLaunchKernelGGL(fill_zero, dim3(ceil_div(L->ncols, 256)), dim3(256), 0, st, b, L->ncols);
@@ -1054,7 +1065,8 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   info->warm_rejected = 0;
   if (!mixed) {
     rfm_status s = run_lsqr(X, anorm, y0, y, opts->atol, opts->btol, opts->maxit, opts->check_every,
-                            opts->use_graph != 0, opts->times, opts->history, st, &hs, &info->warm_rejected);
+                            opts->use_graph != 0, opts->times, opts->history, st, &hs, &info->warm_rejected,
+                            opts->bidiag);
     if (s != RFM_OK) return s;
     s = explicit_check(X, y, st, &hc);
     if (s != RFM_OK) return s;

@@ -445,7 +445,9 @@ __global__ __launch_bounds__(NT) void rf_qrcp(rfm_layout L, const double *__rest
   int *ired = glist + nmax;          // [64]
   unsigned *regact = (unsigned *)(ired + 64);  // [NW]
   int *gcnt = (int *)(regact + NW);             // [2]
-  double *tier = (double *)((((uintptr_t)(gcnt + 2)) + 7) & ~(uintptr_t)7);
+  // the LDS tier starts at the next 8-byte boundary (an element offset from lds, without an
+  // integer round trip, so the compiler keeps it an LDS pointer)
+  double *tier = lds + (((char *)(gcnt + 2) - (char *)lds) + 7) / 8;
 
   const int j = order ? order[blockIdx.x] : blockIdx.x;
   const Blk B = blk(L, j);

@@ -69,7 +69,7 @@ class LsqrOpts(C.Structure):
                 ("check_every", C.c_int32), ("use_graph", C.c_int32),
                 ("times", C.POINTER(KernelTimes)), ("history", _p), ("inner_dtype", C.c_int32),
                 ("max_outer", C.c_int32), ("max_inner", C.c_int64), ("inner_tol", C.c_double),
-                ("adj_tile", C.c_int32)]
+                ("adj_tile", C.c_int32), ("bidiag", _p)]
 
 
 class LsqrInfo(C.Structure):
@@ -333,7 +333,7 @@ def rfm_pack_q(plan: Plan, fact: dict, dtype, Qlow=None):
 def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, maxit=10000,
                    check_every=16, use_graph=0, form=FORM_Q, y=None, ws=None, times=None,
                    history=None, inner_dtype=F64, max_outer=1, max_inner=None, inner_tol=None,
-                   adj_tile=0):
+                   adj_tile=0, bidiag=None):
     """Precision form defaults: one narrow solve to the caller's rule (inner_tol = atol, all
     of maxit), then the binary64 check and finish."""
     L = plan.layout
@@ -352,7 +352,7 @@ def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, max
     opts = LsqrOpts(atol=atol, btol=btol, maxit=maxit, check_every=check_every, use_graph=use_graph,
                     times=C.pointer(times) if times is not None else None, history=_ptr(history),
                     inner_dtype=inner_dtype, max_outer=max_outer, max_inner=max_inner, inner_tol=inner_tol,
-                    adj_tile=adj_tile)
+                    adj_tile=adj_tile, bidiag=_ptr(bidiag))
     info = LsqrInfo()
     nb = _lib.rfm_lsqr_ws_bytes(C.byref(L))
     if ws is None or ws.numel() < nb:

@@ -457,6 +457,34 @@ def test_precision_form_default_is_one_narrow_solve_to_the_rule(rfm):
     assert iw.iters - iw.polish < info.iters - info.polish
 
 
+@pytest.mark.parametrize("name", ["poisson1d", "poisson2d"])
+def test_lsqr_bidiagonalisation_matches_oracle_golub_kahan(rfm, name):
+    """The Golub-Kahan scalars the solve records (alpha_i, beta_i) against the oracle's
+    bidiagonalisation on shared factors, and the condition estimate of B_k against the dense
+    singular values of the operator (a lower bound that never exceeds them)."""
+    from oracle import conditioning as ocond
+
+    inst = I.tiny(name)
+    print(f"[bidiag] {name}", flush=True)
+    rows, blocks, h, facts, plan, fact = _shared_fact(rfm, inst, 1e-8)
+    A = olsqr.QForm(inst.N, rows, [f.Q for f in facts])
+    k = 12
+    bd = torch.zeros(2 * k + 2, dtype=torch.float64, device="cuda")
+    rfm.rfm_lsqr_solve(plan, fact, _dev(h), atol=0.0, btol=0.0, maxit=k, bidiag=bd)
+    torch.cuda.synchronize()
+    g = bd.cpu().numpy()
+    ga, gb = g[0::2], g[1::2]
+    oa, ob = ocond.golub_kahan(A, h, k)
+    print(f"  max rel diff alpha {np.max(np.abs(ga - oa) / oa):.2e} beta {np.max(np.abs(gb - ob) / ob):.2e}",
+          flush=True)
+    assert np.allclose(ga, oa, rtol=1e-9, atol=0) and np.allclose(gb, ob, rtol=1e-9, atol=0)
+    D = np.stack([A.matvec(e) for e in np.eye(A.n)], axis=1)
+    sv = np.linalg.svd(D, compute_uv=False)
+    smax, smin = ocond.ritz_extremes(ga, gb, k)
+    assert smax <= sv[0] * (1 + 1e-9) and smin >= sv[-1] * (1 - 1e-9)
+    assert smax >= 0.99 * sv[0]  # the largest Ritz value converges first (within 1 % in 12 steps here)
+
+
 def test_batching_form_results_independent_of_order_and_launch_shape(rfm):
     """Within each factorisation the results are bitwise independent of the block order and
     the launch shape: the R-first form in cost order, and the direct form with the persistent
