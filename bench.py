@@ -104,11 +104,12 @@ def cpu_baseline(inst, tau, nblocks):
 
 
 def conditioning_study(args):
-    """Filter drop fraction and the condition of the preconditioned operator across tau (the
-    columns of the paper's tables).  For each workload and tau: the filter, then k steps of the
-    solver's Golub-Kahan bidiagonalisation on the workload's right-hand side (LSQR with the stop
-    rule off, recording alpha_i, beta_i); sigma_max(B_k) / sigma_min(B_k) is a lower bound of
-    kappa(A_hat) that grows with k (reported at k/4, k/2, k)."""
+    """Filter drop fraction and condition estimates across tau (the columns of the paper's
+    tables): kappa(M) of the assembled matrix, kappa(M_hat) of the kept columns, and
+    kappa(M_hat S^{-1}) of the preconditioned operator.  Each comes from k steps of the solver's
+    Golub-Kahan bidiagonalisation on the workload's right-hand side (LSQR with the stop rule off,
+    recording alpha_i, beta_i; the M forms without the preconditioner); sigma_max(B_k) /
+    sigma_min(B_k) is a lower bound of kappa that grows with k (reported at k/4, k/2, k)."""
     import torch
 
     from paper_2506_17626_amd import instances as I
@@ -117,14 +118,35 @@ def conditioning_study(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     k = args.cond_steps
-    out = {"study": "conditioning", "steps": k, "taus": [], "workloads": {}}
     taus = [1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12]
-    out["taus"] = taus
+    out = {"study": "conditioning", "steps": k, "taus": taus, "workloads": {}}
+
+    def bounds(plan, fact, h, form):
+        bd = torch.zeros(2 * k + 2, dtype=torch.float64, device=dev)
+        _, info = rfm.rfm_lsqr_solve(plan, fact, h, atol=0.0, btol=0.0, maxit=k, check_every=64, use_graph=1,
+                                     form=form, bidiag=bd)
+        torch.cuda.synchronize()
+        g = bd.cpu().numpy()
+        ke = int(info.iters)  # steps taken (a breakdown ends the process early)
+        est = {}
+        for kk in sorted({max(1, ke // 4), max(1, ke // 2), ke}):
+            B = np.zeros((kk + 1, kk))
+            B[np.arange(kk), np.arange(kk)] = g[0:2 * kk:2]
+            B[np.arange(1, kk + 1), np.arange(kk)] = g[3:2 * kk + 2:2]
+            sv = np.linalg.svd(B, compute_uv=False)
+            est[str(kk)] = float(sv[0] / sv[-1])
+        return {"steps": ke, "kappa_lower_bound": est}
+
     for name in args.cond_workloads.split(","):
         inst = I.workload(name, seed=args.seed)
         plan = rfm.plan_instance(inst)
         prob = rfm.problem_tensors(inst)
         M, h = rfm.rfm_assemble(plan, prob)
+        K = np.diff(plan.host["feat_off"])
+        ncols = int(K.sum())
+        every = {"M": M, "rank": torch.from_numpy(K.astype(np.int32)).to(dev),
+                 "kept": torch.from_numpy(np.concatenate([np.arange(kj) for kj in K]).astype(np.int32)).to(dev)}
+        km = bounds(plan, every, h, rfm.FORM_M)
         rows = []
         for tau in taus:
             fact = rfm.rfm_rrqr_filter(plan, M, tau)
@@ -134,29 +156,16 @@ def conditioning_study(args):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             kept = int(fact["rank"].sum())
-            bd = torch.zeros(2 * k + 2, dtype=torch.float64, device=dev)
-            _, info = rfm.rfm_lsqr_solve(plan, fact, h, atol=0.0, btol=0.0, maxit=k, check_every=64,
-                                         use_graph=1, bidiag=bd)
-            torch.cuda.synchronize()
-            g = bd.cpu().numpy()
-            ke = int(info.iters)  # steps taken (a breakdown ends the process early)
-            est = {}
-            for kk in sorted({max(1, ke // 4), max(1, ke // 2), ke}):
-                B = np.zeros((kk + 1, kk))
-                B[np.arange(kk), np.arange(kk)] = g[0:2 * kk:2]
-                B[np.arange(1, kk + 1), np.arange(kk)] = g[3:2 * kk + 2:2]
-                sv = np.linalg.svd(B, compute_uv=False)
-                est[kk] = (float(sv[0]), float(sv[-1]))
-            row = {"tau": tau, "kept": kept, "columns": int(sum(np.diff(plan.host["feat_off"]))),
-                   "drop_pct": 100.0 * (1 - kept / max(1, int(sum(np.diff(plan.host["feat_off"]))))),
-                   "filter_ms": 1e3 * (t1 - t0),
-                   "steps": ke, "stop": int(info.stop), "sigma_max": est[ke][0], "sigma_min_est": est[ke][1],
-                   "kappa_lower_bound": {str(kk): v[0] / v[1] for kk, v in est.items()}}
+            row = {"tau": tau, "kept": kept, "columns": ncols, "drop_pct": 100.0 * (1 - kept / max(1, ncols)),
+                   "filter_ms": 1e3 * (t1 - t0), "M_hat": bounds(plan, dict(fact, M=M), h, rfm.FORM_M),
+                   "M_hat_S_inv": bounds(plan, fact, h, rfm.FORM_Q)}
             rows.append(row)
-            print(f"[conditioning] {name} tau={tau:g}: dropped {row['drop_pct']:.1f} %, kappa(A_hat) >= "
-                  f"{row['kappa_lower_bound'][str(ke)]:.3e} after {ke} steps", file=sys.stderr, flush=True)
-        out["workloads"][name] = rows
-        del M
+            lb = lambda e: e["kappa_lower_bound"][str(e["steps"])]
+            print(f"[conditioning] {name} tau={tau:g}: dropped {row['drop_pct']:.1f} %, kappa >= M {lb(km):.2e}, "
+                  f"M_hat {lb(row['M_hat']):.2e}, M_hat S^-1 {lb(row['M_hat_S_inv']):.2e} after {k} steps",
+                  file=sys.stderr, flush=True)
+        out["workloads"][name] = {"M": km, "taus": rows}
+        del M, every
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 

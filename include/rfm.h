@@ -201,18 +201,23 @@ rfm_status rfm_rrqr_filter_tuned(const rfm_layout *L, const double *M, double ta
                                  const int32_t *order, const rfm_tuning *tune, void *ws,
                                  size_t ws_bytes, void *stream);
 
-/* Operator of the preconditioned system M_hat S^{-1} (Proposition 3.1). */
+/* Operator of the preconditioned system M_hat S^{-1} (Proposition 3.1), or of the system
+ * without the preconditioner. */
 typedef enum {
   RFM_FORM_Q = 0,         /* explicit Q_hat_j: A = sum_j V_j^T Q_hat_j W_hat_j        */
-  RFM_FORM_R = 1          /* kept columns of M_j with back-substitution by R_hat_j   */
+  RFM_FORM_R = 1,         /* kept columns of M_j with back-substitution by R_hat_j   */
+  RFM_FORM_M = 2          /* kept columns of M_j alone: A = M_hat, no preconditioner
+                             (for condition estimates and comparisons; with kept = all
+                             columns and rank_j = K_j it is M itself).  The stopping rule's
+                             ||A|| is ||M_hat||_F, computed on the device */
 } rfm_form;
 
 typedef struct {
   int32_t form;           /* rfm_form                                       */
   const int32_t *rank;    /* device [J]                                     */
   const double *Q;        /* device [nnz]  (RFM_FORM_Q)                     */
-  const double *M;        /* device [nnz]  (RFM_FORM_R)                     */
-  const int32_t *kept;    /* device [ncols] (RFM_FORM_R)                    */
+  const double *M;        /* device [nnz]  (RFM_FORM_R, RFM_FORM_M)         */
+  const int32_t *kept;    /* device [ncols] (RFM_FORM_R, RFM_FORM_M)        */
   const double *R;        /* device [nrsq] (RFM_FORM_R)                     */
   const void *Qlow;       /* device [nnz] elements of low_dtype, nullable: narrow copy of
                              Q_hat from rfm_pack_q, used by the precision form */

@@ -55,6 +55,12 @@ class QForm:
         return np.concatenate([Q.T @ u[r] for r, Q in zip(self.rows, self.Qs)]) if self.Qs else np.zeros(0)
 
 
+class MForm(QForm):
+    """A = M_hat = sum_j V_j^T M_hat_j W_hat_j, the kept columns of M_j without the
+    preconditioner: the same block sum as the Q form with M_hat_j in place of Q_hat_j (for
+    condition estimates of the unpreconditioned system)."""
+
+
 class RForm:
     """A = M_hat S^{-1}, S^{-1} applied block by block by back-substitution with R_hat_j."""
 

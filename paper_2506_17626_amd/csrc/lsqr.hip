@@ -119,6 +119,20 @@ __global__ void block_desc(rfm_layout L, const int32_t *__restrict__ rank, Block
   d[j] = b;
 }
 
+// ||M_hat_j||_F^2 over the kept columns of block j, one workgroup per block, fixed order.
+__global__ __launch_bounds__(256) void kept_fro2(const double *__restrict__ M, const int32_t *__restrict__ kept,
+                                                 const BlockDesc *__restrict__ desc, double *out) {
+  __shared__ double red[256 / kWave];
+  const BlockDesc d = desc[blockIdx.x];
+  double s = 0.0;
+  for (int k = 0; k < d.r; ++k) {
+    const double *__restrict__ c = M + d.base + (int64_t)kept[d.f0 + k] * d.m;
+    for (int i = threadIdx.x; i < d.m; i += 256) s = fma(c[i], c[i], s);
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 __global__ void fill_zero(double *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -741,11 +755,14 @@ struct Launcher {
   Work W;
   int ct;
   bool rform;
+  bool mform = false;          // the kept columns of M without the preconditioner
   int dtype = RFM_F64;         // operand of the Q form: RFM_F64 (A->Q) or a narrow copy
   const void *Qlow = nullptr;  // RFM_F32 / RFM_BF16 copy of Q_hat in the block layout
 
   size_t fwd_lds() const { return (size_t)(L->max_cols > 0 ? L->max_cols : 1) * (sizeof(double) + sizeof(int)); }
-  size_t adj_lds() const { return rform ? sizeof(int) * (size_t)(L->max_cols > 0 ? L->max_cols : 1) : 0; }
+  size_t adj_lds() const {
+    return (rform || mform) ? sizeof(int) * (size_t)(L->max_cols > 0 ? L->max_cols : 1) : 0;
+  }
   size_t tri_lds() const { return sizeof(double) * ((size_t)(L->max_cols > 0 ? L->max_cols : 1) + kTri * kTri); }
   unsigned g_rows() const { return ceil_div(L->N, kVecThreads); }
   unsigned g_cols() const { return ceil_div(L->ncols, kVecThreads); }
@@ -764,7 +781,10 @@ struct Launcher {
     const int flags = (mode == ITER) ? (F_CHECK_DONE | F_DIV_ALPHA) : 0;
     const dim3 grid(ceil_div(L->max_rows, kRowTile), L->J);
     const int32_t *nk = nullptr;
-    if (!rform && dtype == RFM_F32) {
+    if (mform) {
+      launch(fwd_local<double, true>, grid, dim3(kRowTile), fwd_lds(), s, e0, e1, *L, (const double *)A->M, A->kept,
+             (const BlockDesc *)W.desc, vin, W.t, (const State *)st, flags);
+    } else if (!rform && dtype == RFM_F32) {
       launch(fwd_local<float, false>, grid, dim3(kRowTile), fwd_lds(), s, e0, e1, *L, (const float *)Qlow, nk,
              (const BlockDesc *)W.desc, vin, W.t, (const State *)st, flags);
     } else if (!rform && dtype == RFM_BF16) {
@@ -800,7 +820,10 @@ struct Launcher {
     const int32_t *nk = nullptr;
     const BlockDesc *dsc = W.desc;
     const State *cst = st;
-    if (!rform && dtype == RFM_F32) {
+    if (mform) {
+      launch(adj_local<double, true>, grid, dim3(kAdjThreads), adj_lds(), s, e0, e1, *L, (const double *)A->M,
+             A->kept, dsc, ubk, qcur, qnew, pout, ct, cst, flags);
+    } else if (!rform && dtype == RFM_F32) {
       launch(adj_local<float, false>, grid, dim3(kAdjThreads), adj_lds(), s, e0, e1, *L, (const float *)Qlow, nk,
              dsc, ubk, qcur, qnew, pout, ct, cst, flags);
     } else if (!rform && dtype == RFM_BF16) {
@@ -1019,13 +1042,17 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   rfm_status s0 = check_layout(L, "rfm_lsqr_solve");
   if (s0 != RFM_OK) return s0;
   if (!A || !A->rank || !opts || !h || !y || !info) return fail(RFM_EINVAL, "rfm_lsqr_solve: null pointer");
-  if (A->form != RFM_FORM_Q && A->form != RFM_FORM_R) return fail(RFM_EINVAL, "rfm_lsqr_solve: bad form");
+  if (A->form != RFM_FORM_Q && A->form != RFM_FORM_R && A->form != RFM_FORM_M)
+    return fail(RFM_EINVAL, "rfm_lsqr_solve: bad form");
+  if (A->form == RFM_FORM_M && ((L->nnz > 0 && !A->M) || !A->kept))
+    return fail(RFM_EINVAL, "rfm_lsqr_solve: M form needs M and kept");
   if (A->form == RFM_FORM_Q && L->nnz > 0 && !A->Q) return fail(RFM_EINVAL, "rfm_lsqr_solve: null Q");
   if (A->form == RFM_FORM_R && ((L->nnz > 0 && !A->M) || !A->kept || (L->nrsq > 0 && !A->R)))
     return fail(RFM_EINVAL, "rfm_lsqr_solve: R form needs M, kept and R");
   if (opts->maxit < 1 || opts->check_every < 1 || !(opts->atol >= 0) || !(opts->btol >= 0))
     return fail(RFM_EINVAL, "rfm_lsqr_solve: bad options");
   const bool mixed = opts->inner_dtype != RFM_F64;
+  if (mixed && A->form != RFM_FORM_Q) return fail(RFM_EINVAL, "rfm_lsqr_solve: the precision form needs the Q form");
   if (mixed) {
     if (opts->inner_dtype != RFM_F32 && opts->inner_dtype != RFM_BF16)
       return fail(RFM_EINVAL, "rfm_lsqr_solve: inner_dtype must be RFM_F64, RFM_F32 or RFM_BF16");
@@ -1046,17 +1073,32 @@ extern "C" rfm_status rfm_lsqr_solve(const rfm_layout *L, const rfm_operator *A,
   X.h = h;
   X.ct = opts->adj_tile > 0 ? ((opts->adj_tile + kAdjQuantum - 1) / kAdjQuantum) * kAdjQuantum : adj_tile(L);
   X.rform = (A->form == RFM_FORM_R);
+  X.mform = (A->form == RFM_FORM_M);
   carve(L, (char *)ws, &X.W);
   hipLaunchKernelGGL(block_desc, dim3(ceil_div(L->J, 256)), dim3(256), 0, st, *L, A->rank, X.W.desc);
   RFM_LAUNCH_CHECK();
 
-  // ||A||_F = sqrt(sum_j r_j): the Q form has unit-norm columns
-  std::vector<int32_t> hrank(L->J);
-  RFM_HIP_TRY(hipMemcpyAsync(hrank.data(), A->rank, sizeof(int32_t) * L->J, hipMemcpyDeviceToHost, st));
-  RFM_HIP_TRY(hipStreamSynchronize(st));
-  double nr = 0.0;
-  for (int32_t j = 0; j < L->J; ++j) nr += hrank[j];
-  const double anorm = std::sqrt(nr);
+  // ||A||_F: sqrt(sum_j r_j) for the Q and R forms (unit-norm columns); for the M form the
+  // kept columns' Frobenius norm, per block on the device, summed here in block order
+  double anorm;
+  if (X.mform) {
+    std::vector<double> hf(L->J);
+    hipLaunchKernelGGL(kept_fro2, dim3(L->J), dim3(256), 0, st, A->M, A->kept, (const BlockDesc *)X.W.desc,
+                       X.W.part);
+    RFM_LAUNCH_CHECK();
+    RFM_HIP_TRY(hipMemcpyAsync(hf.data(), X.W.part, sizeof(double) * L->J, hipMemcpyDeviceToHost, st));
+    RFM_HIP_TRY(hipStreamSynchronize(st));
+    double f2 = 0.0;
+    for (int32_t j = 0; j < L->J; ++j) f2 += hf[j];
+    anorm = std::sqrt(f2);
+  } else {
+    std::vector<int32_t> hrank(L->J);
+    RFM_HIP_TRY(hipMemcpyAsync(hrank.data(), A->rank, sizeof(int32_t) * L->J, hipMemcpyDeviceToHost, st));
+    RFM_HIP_TRY(hipStreamSynchronize(st));
+    double nr = 0.0;
+    for (int32_t j = 0; j < L->J; ++j) nr += hrank[j];
+    anorm = std::sqrt(nr);
+  }
   if (opts->times) *opts->times = rfm_kernel_times{};
 
   State hs{}, hc{};

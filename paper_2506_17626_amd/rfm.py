@@ -20,7 +20,7 @@ if not os.path.exists(_LIB_PATH):
 _lib = C.CDLL(_LIB_PATH)
 
 RFM_OK, RFM_EINVAL, RFM_EHIP, RFM_ENOTCONV, RFM_EUNSUPPORTED = 0, 1, 3, 4, 5
-FORM_Q, FORM_R = 0, 1
+FORM_Q, FORM_R, FORM_M = 0, 1, 2
 RRQR_AUTO, RRQR_DIRECT, RRQR_RFIRST = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
 
@@ -345,9 +345,8 @@ def rfm_lsqr_solve(plan: Plan, fact: dict, h, y0=None, atol=1e-8, btol=1e-8, max
     y = torch.empty(max(L.ncols, 1), dtype=torch.float64, device=dev) if y is None else y
     qlow = fact.get("Qlow")
     low_dtype = {torch.float32: F32, torch.bfloat16: BF16}.get(qlow.dtype, F64) if qlow is not None else F64
-    op = Operator(form=form, rank=fact["rank"].data_ptr(), Q=fact["Q"].data_ptr(),
-                  M=fact["M"].data_ptr() if fact.get("M") is not None else 0,
-                  kept=fact["kept"].data_ptr(), R=fact["R"].data_ptr(),
+    ptr = lambda key: fact[key].data_ptr() if fact.get(key) is not None else 0
+    op = Operator(form=form, rank=fact["rank"].data_ptr(), Q=ptr("Q"), M=ptr("M"), kept=ptr("kept"), R=ptr("R"),
                   Qlow=qlow.data_ptr() if qlow is not None else 0, low_dtype=low_dtype)
     opts = LsqrOpts(atol=atol, btol=btol, maxit=maxit, check_every=check_every, use_graph=use_graph,
                     times=C.pointer(times) if times is not None else None, history=_ptr(history),

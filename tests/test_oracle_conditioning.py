@@ -71,3 +71,27 @@ def test_bidiagonal_shape_and_entries():
     assert np.array_equal(np.diag(B), [1.0, 2.0, 3.0])
     assert np.array_equal(np.diag(B, -1), [5.0, 6.0, 7.0])
     assert np.count_nonzero(B) == 6
+
+
+def test_m_form_is_the_block_sum_of_kept_columns():
+    """The unpreconditioned operator: column (j, k) is the kept column of M_j on the rows of
+    block j, and rmatvec is its adjoint."""
+    from oracle import assembly, rrqr
+    from oracle import lsqr as olsqr
+    from paper_2506_17626_amd import instances as I
+
+    inst = I.tiny("poisson2d")
+    rows, blocks, h = assembly.assemble(inst)
+    facts = rrqr.filter_blocks(blocks, 1e-8)
+    A = olsqr.MForm(inst.N, rows, [b[:, f.kept] for b, f in zip(blocks, facts)])
+    off = np.concatenate([[0], np.cumsum([f.rank for f in facts])])
+    j = int(np.argmax([f.rank for f in facts]))
+    k = facts[j].rank // 2
+    e = np.zeros(A.n)
+    e[off[j] + k] = 1.0
+    col = np.zeros(inst.N)
+    col[rows[j]] = blocks[j][:, facts[j].kept[k]]
+    assert np.array_equal(A.matvec(e), col)
+    rng = np.random.default_rng(2)
+    x, u = rng.standard_normal(A.n), rng.standard_normal(inst.N)
+    assert np.isclose(A.matvec(x) @ u, x @ A.rmatvec(u), rtol=1e-12)
