@@ -137,6 +137,40 @@ def conditioning_study(args):
             est[str(kk)] = float(sv[0] / sv[-1])
         return {"steps": ke, "kappa_lower_bound": est}
 
+    # 1D: the condition of the preconditioned operator against the number of features K and the
+    # overlap rho, and the strip bound of Theorem 3.2 (alpha = max_j ||Q_hat_j^T Q_hat_{j+1}|| over
+    # the rows two neighbours share; kappa <= ((1 + 2 alpha) / (1 - 2 alpha))^(1/2) when 2 alpha < 1),
+    # alpha measured from the device's Q_hat
+    sweep = []
+    for K in (16, 32, 64, 128):
+        for rho in (0.1, 0.2, 0.3, 0.5):
+            inst = I.poisson1d(K=K, rho=rho, seed=args.seed)
+            plan = rfm.plan_instance(inst)
+            prob = rfm.problem_tensors(inst)
+            M, h = rfm.rfm_assemble(plan, prob)
+            fact = rfm.rfm_rrqr_filter(plan, M, 1e-12)
+            Qh = fact["Q"].cpu().numpy()
+            rk = fact["rank"].cpu().numpy()
+            ro, rows_, bo = plan.host["row_off"], plan.host["rows"], plan.host["blk_off"]
+            blk = []
+            for j in range(inst.J):
+                m = int(ro[j + 1] - ro[j])
+                blk.append((rows_[ro[j]:ro[j + 1]], Qh[bo[j]:bo[j] + m * int(rk[j])].reshape(int(rk[j]), m).T))
+            alpha = 0.0
+            for j in range(inst.J - 1):
+                (ra, Qa), (rb, Qb) = blk[j], blk[j + 1]
+                common, ia, ib = np.intersect1d(ra, rb, return_indices=True)
+                if len(common) and Qa.shape[1] and Qb.shape[1]:
+                    alpha = max(alpha, float(np.linalg.norm(Qa[ia].T @ Qb[ib], 2)))
+            b = bounds(plan, fact, h, rfm.FORM_Q)
+            ncols = int(np.diff(plan.host["feat_off"]).sum())
+            sweep.append({"K": K, "rho": rho, "kept": int(rk.sum()), "drop_pct": 100.0 * (1 - rk.sum() / ncols),
+                          "alpha": alpha, "thm32_bound": float(np.sqrt((1 + 2 * alpha) / (1 - 2 * alpha)))
+                          if 2 * alpha < 1 else None, "M_hat_S_inv": b})
+            print(f"[conditioning] 1D K={K} rho={rho}: dropped {sweep[-1]['drop_pct']:.1f} %, alpha {alpha:.3f}, "
+                  f"kappa >= {b['kappa_lower_bound'][str(b['steps'])]:.3e}", file=sys.stderr, flush=True)
+    out["poisson1d_K_rho"] = sweep
+
     for name in args.cond_workloads.split(","):
         inst = I.workload(name, seed=args.seed)
         plan = rfm.plan_instance(inst)
