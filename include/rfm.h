@@ -87,8 +87,17 @@ typedef struct {
   const int64_t *rsq_off; /* device [J+1] prefix sums of K_j^2              */
 } rfm_layout;
 
+/* Activation Xi of the random features (eq. fcn_depth_h).  tanh is the baseline of every
+ * problem in Section 5; the ablation rows of its three results tables use the sigmoid and
+ * sin instead. */
+typedef enum {
+  RFM_ACT_TANH = 0,       /* tanh(s)                                        */
+  RFM_ACT_SIGMOID = 1,    /* 1 / (1 + exp(-s))                              */
+  RFM_ACT_SIN = 2         /* sin(s)                                         */
+} rfm_activation;
+
 /* Discretised problem (Section 2.1 and Section 4.2): subdomain geometry, random
- * features phi_jk = tanh(w_jk . (x - mu_j)/hw_j + b_jk) (eq. fcn_depth_h, depth 1,
+ * features phi_jk = act(w_jk . (x - mu_j)/hw_j + b_jk) (eq. fcn_depth_h, depth 1,
  * inputs normalised to [-1,1] per subdomain), points and per-row data. */
 typedef struct {
   const double *x;        /* device [N*d] row-major points                 */
@@ -101,6 +110,7 @@ typedef struct {
   const double *b;        /* device [ncols] feature biases                 */
   double kappa;           /* RFM_OP_HEAT diffusion constant                */
   double ksq;             /* RFM_OP_HELMHOLTZ k^2                          */
+  int32_t activation;     /* rfm_activation of the features (0 = tanh)     */
 } rfm_problem;
 
 /* Planning (sync, host only).  Builds the supports I_j of eq. DomainDecomp from host

@@ -4,8 +4,10 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 Follows the paper's statement of the discretised problem:
 * ansatz u(x) = sum_j w_j(x) sum_k a_jk phi_jk(x)            (eq. elm_solution)
-* phi_jk = tanh(w_jk . xn + b_jk) on the input normalised to [-1,1] over the
-  subdomain (eq. fcn_depth_h with depth 1; Section 4.2, network architecture)
+* phi_jk = Xi(w_jk . xn + b_jk) on the input normalised to [-1,1] over the
+  subdomain (eq. fcn_depth_h with depth 1; Section 4.2, network architecture), with the
+  activation Xi = tanh (every baseline of Section 5) or the sigmoid or sin of the ablation
+  rows of Section 5's results tables
 * w_j = what_j / sum_i what_i with
   what_j = prod_d (1 + cos(pi (x_d - mu_jd) / sigma_jd))^2 on |x_d - mu_jd| < sigma_jd
   (eq. used_window_function_nd, with the parenthesis read as (x - mu)/sigma)
@@ -101,16 +103,37 @@ def windows(inst, rows_per_block=None):
     return out
 
 
-def features(x: np.ndarray, mu_j, hw_j, wk: np.ndarray, bk: np.ndarray):
-    """phi = tanh(s), s = sum_i w_i (x_i - mu_i)/sigma_i + b; returns phi, d_i phi, d_ii phi
+ACTIVATIONS = ("tanh", "sigmoid", "sin")
+
+
+def activation(name: str, s: np.ndarray):
+    """Xi(s), Xi'(s), Xi''(s) for the activations of Section 5:
+    tanh:    t = tanh s,           t' = 1 - t^2,        t'' = -2 t t'
+    sigmoid: t = 1 / (1 + e^-s),   t' = t (1 - t),      t'' = t' (1 - 2 t)
+    sin:     t = sin s,            t' = cos s,          t'' = -sin s"""
+    if name == "tanh":
+        t = np.tanh(s)
+        g = 1.0 - t * t
+        return t, g, -2.0 * t * g
+    if name == "sigmoid":
+        with np.errstate(over="ignore"):          # exp(-s) = inf gives t = 0 exactly
+            t = 1.0 / (1.0 + np.exp(-s))
+        g = t * (1.0 - t)
+        return t, g, g * (1.0 - 2.0 * t)
+    if name == "sin":
+        return np.sin(s), np.cos(s), -np.sin(s)
+    raise ValueError(f"unknown activation {name!r}")
+
+
+def features(x: np.ndarray, mu_j, hw_j, wk: np.ndarray, bk: np.ndarray, act: str = "tanh"):
+    """phi = Xi(s), s = sum_i w_i (x_i - mu_i)/sigma_i + b; returns phi, d_i phi, d_ii phi
     as arrays [m, K], [m, K, d], [m, K, d]."""
     xn = (x - mu_j[None, :]) / hw_j[None, :]
     s = xn @ wk.T + bk[None, :]
-    t = np.tanh(s)
-    g = 1.0 - t * t
+    t, g, gg = activation(act, s)
     scale = wk / hw_j[None, :]                      # [K, d]: dS/dx_i
     dphi = g[:, :, None] * scale[None, :, :]
-    ddphi = (-2.0 * t * g)[:, :, None] * (scale * scale)[None, :, :]
+    ddphi = gg[:, :, None] * (scale * scale)[None, :, :]
     return t, dphi, ddphi
 
 
@@ -145,7 +168,8 @@ def assemble(inst):
         k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
         x = inst.x[r]
         w, dw, ddw = wins[j]
-        phi, dphi, ddphi = features(x, inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1])
+        phi, dphi, ddphi = features(x, inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1],
+                                    inst.activation)
         psi = w[:, None] * phi
         dpsi = dw[:, None, :] * phi[:, :, None] + w[:, None, None] * dphi
         ddpsi = (ddw[:, None, :] * phi[:, :, None] + 2.0 * dw[:, None, :] * dphi
@@ -163,8 +187,9 @@ def entry_error_scale(inst, rows, j):
     the absolute values of its terms (|a - b| -> |a| + |b|, |a b| -> |a| |b|), the
     usual running bound of forward rounding-error analysis: an evaluation of the
     formula in binary64 with n rounded operations on the path to an entry differs from
-    the exact value by at most about n u times this magnitude.  tanh contributes its
-    condition number: |d tanh(s)| <= (1 - t^2)|ds| + |t| u.
+    the exact value by at most about n u times this magnitude.  The activation and its
+    derivatives contribute their sensitivity to the rounding of s:
+    |d Xi^(i)(s)| <= |Xi^(i+1)(s)| |ds| + |Xi^(i)(s)| u, with |ds| <= sarg u.
     """
     d = inst.d
     N = inst.N
@@ -209,13 +234,10 @@ def entry_error_scale(inst, rows, j):
     wk, bk = inst.w[k0:k1], inst.b[k0:k1]
     xn = (inst.x[r] - inst.mu[j][None, :]) / inst.hw[j][None, :]
     sarg = np.abs(xn) @ np.abs(wk).T + np.abs(bk)[None, :]
-    t = np.tanh(xn @ wk.T + bk[None, :])
-    g = 1.0 - t * t
-    ta = np.abs(t) + g * sarg
-    ga = 1.0 + t * t + 2.0 * np.abs(t) * g * sarg
+    ta, ga, gga = _activation_bounds(inst.activation, xn @ wk.T + bk[None, :], sarg)
     sc = np.abs(wk / inst.hw[j][None, :])
     dphia = ga[:, :, None] * sc[None, :, :]
-    ddphia = (2.0 * ta * ga)[:, :, None] * (sc * sc)[None, :, :]
+    ddphia = gga[:, :, None] * (sc * sc)[None, :, :]
     psia = wa[:, None] * ta
     dpsia = dwa[:, None, :] * ta[:, :, None] + wa[:, None, None] * dphia
     ddpsia = ddwa[:, None, :] * ta[:, :, None] + 2.0 * dwa[:, None, :] * dphia + wa[:, None, None] * ddphia
@@ -226,6 +248,30 @@ def entry_error_scale(inst, rows, j):
     out = np.where(op == OP_HEAT, dpsia[:, :, d - 1] + abs(inst.kappa) * spatial, out)
     out = np.where(op == OP_HELMHOLTZ, lap + abs(inst.ksq) * psia, out)
     return np.abs(inst.weight[r])[:, None] * out
+
+
+def _activation_bounds(name: str, s: np.ndarray, sarg: np.ndarray):
+    """Running bounds of Xi, Xi', Xi'' at s (|s| evaluated term by term is sarg): each is the
+    absolute-value evaluation of its formula plus the next derivative times sarg."""
+    if name == "tanh":
+        t = np.tanh(s)
+        g = 1.0 - t * t
+        ta = np.abs(t) + g * sarg
+        ga = 1.0 + t * t + 2.0 * np.abs(t) * g * sarg
+        return ta, ga, 2.0 * ta * ga
+    if name == "sigmoid":
+        with np.errstate(over="ignore"):
+            t = 1.0 / (1.0 + np.exp(-s))
+        g = t * (1.0 - t)
+        g2 = np.abs(g * (1.0 - 2.0 * t))
+        g3 = np.abs(g * (1.0 - 6.0 * g))
+        ta = t + g * (sarg + 1.0)               # exp's own rounding moves t by t' u
+        ga = t * (1.0 + t) + g2 * (sarg + 1.0)
+        return ta, ga, ga * (1.0 + 2.0 * ta) + g3 * (sarg + 1.0)
+    if name == "sin":
+        sn, cs = np.abs(np.sin(s)), np.abs(np.cos(s))
+        return sn + cs * sarg, cs + sn * sarg, sn + cs * sarg
+    raise ValueError(f"unknown activation {name!r}")
 
 
 def global_dense(inst, rows, blocks):

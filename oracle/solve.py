@@ -57,7 +57,8 @@ def evaluate(inst, a: np.ndarray, xt: np.ndarray) -> np.ndarray:
         if r.size == 0:
             continue
         k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
-        phi, _, _ = assembly.features(xt[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1])
+        phi, _, _ = assembly.features(xt[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1],
+                                      inst.activation)
         u[r] += (what[j] / S[r]) * (phi @ a[k0:k1])
     return u
 

@@ -8,7 +8,8 @@
 // assemble_entries: lane <-> row of one block, so the column-major block is written
 //   with coalesced 64-wide stores; each thread produces a run of features for its row,
 //   reusing the row's point and window data.  Entry = s_r Op_r[w_j phi_jk](x_r) by the
-//   product rule with phi = tanh(w . xn + b), xn = (x - mu_j)/hw_j (eq. fcn_depth_h).
+//   product rule with phi = Xi(w . xn + b), xn = (x - mu_j)/hw_j (eq. fcn_depth_h), Xi the
+//   problem's activation (tanh, sigmoid or sin).
 // Both run in binary64, or in binary32 for the precision form (rfm_assemble_low), whose
 // entries are stored as binary32 or bfloat16.
 #include "common.hpp"
@@ -146,15 +147,15 @@ __global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, 
 #pragma unroll
     for (int a = 0; a < D; ++a) s += xn[a] * (Tc)wk[a];
     s += (Tc)P.b[f0 + k];
-    const Tc t = tanh(s);
-    const Tc g = (Tc)1 - t * t;
+    Tc t, g, gg;  // phi, phi', phi'' of the activation at s
+    activation3<Tc>(P.activation, s, t, g, gg);
     const Tc psi = w * t;
     Tc lap = 0, spatial = 0, dlast = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const Tc sc = (Tc)wk[a] / hwj[a];
       const Tc dphi = g * sc;
-      const Tc ddphi = ((Tc)-2 * t * g) * (sc * sc);
+      const Tc ddphi = gg * (sc * sc);
       const Tc dpsi = dw[a] * t + w * dphi;
       const Tc ddpsi = ddw[a] * t + (Tc)2 * dw[a] * dphi + w * ddphi;
       lap += ddpsi;

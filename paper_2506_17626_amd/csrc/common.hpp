@@ -97,6 +97,31 @@ __device__ __forceinline__ double block_sum(double v, double *scratch) {
   return t;
 }
 
+// Feature activation and its first two derivatives at s (rfm_activation): phi, phi', phi''.
+template <typename T>
+__device__ __forceinline__ void activation3(int act, T s, T &t, T &g, T &gg) {
+  if (act == RFM_ACT_SIN) {
+    t = sin(s);
+    g = cos(s);
+    gg = -t;
+  } else if (act == RFM_ACT_SIGMOID) {
+    t = (T)1 / ((T)1 + exp(-s));
+    g = t * ((T)1 - t);
+    gg = g * ((T)1 - (T)2 * t);
+  } else {
+    t = tanh(s);
+    g = (T)1 - t * t;
+    gg = (T)-2 * t * g;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T activation1(int act, T s) {
+  if (act == RFM_ACT_SIN) return sin(s);
+  if (act == RFM_ACT_SIGMOID) return (T)1 / ((T)1 + exp(-s));
+  return tanh(s);
+}
+
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace rfm

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kEvalThreads) void eval_points(rfm_layout L, rfm_pr
         double s = P.b[k];
 #pragma unroll
         for (int i = 0; i < D; ++i) s += xn[i] * P.w[k * D + i];
-        acc += a[k] * tanh(s);
+        acc += a[k] * activation1<double>(P.activation, s);
       }
       u += w * acc;
     }

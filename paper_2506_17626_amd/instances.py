@@ -10,7 +10,8 @@ solver): both the CPU oracle and the HIP path consume the arrays it returns.
 Problem statement: a linear PDE with linear boundary operators (paper,
 Section 2.1), discretised by a regular overlapping decomposition (Section 4.2,
 eq. dd) with cosine windows (eq. used_window_function_nd) and random
-one-hidden-layer tanh features (eq. fcn_depth_h with h=1), rows weighted as in
+one-hidden-layer features (eq. fcn_depth_h with h=1; tanh, or the sigmoid or sin of
+Section 5's ablations), rows weighted as in
 eq. ELMFBPINN_ls (interior rows by 1/sqrt(N_I), boundary set l by
 sqrt(lambda_l / N_B^(l)) with lambda_l = 1).
 
@@ -30,7 +31,7 @@ Box-Muller) so that the streams do not depend on NumPy's distribution code.
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -90,6 +91,7 @@ class Instance:
     exact: object = None    # callable u(x[N,d]) -> [N]
     test_grid: int = 0      # points per dim of the cell-centred test grid
     meta: dict = field(default_factory=dict)
+    activation: str = "tanh"  # feature activation: "tanh", "sigmoid" or "sin"
 
     @property
     def N(self) -> int:
@@ -327,6 +329,14 @@ def workload(name: str, seed: int = 0) -> Instance:
     if name == "poisson2d_family":    # geometry of poisson2d; RHS from poisson2d_family_rhs
         return poisson2d(seed=seed, name="poisson2d_family")
     raise KeyError(name)
+
+
+def with_activation(inst: Instance, activation: str) -> Instance:
+    """The same instance with the features' activation replaced (Section 5's ablations:
+    the sigmoid and sin in place of tanh); weights, biases and points are unchanged."""
+    if activation not in ("tanh", "sigmoid", "sin"):
+        raise ValueError(f"unknown activation {activation!r}")
+    return replace(inst, activation=activation, name=f"{inst.name}_{activation}")
 
 
 def tiny(name: str, seed: int = 0) -> Instance:

@@ -40,7 +40,9 @@ class Layout(C.Structure):
 
 class Problem(C.Structure):
     _fields_ = [("x", _p), ("rowop", _p), ("weight", _p), ("rhs", _p), ("mu", _p), ("hw", _p),
-                ("w", _p), ("b", _p), ("kappa", C.c_double), ("ksq", C.c_double)]
+                ("w", _p), ("b", _p), ("kappa", C.c_double), ("ksq", C.c_double), ("activation", C.c_int32)]
+
+ACTIVATIONS = {"tanh": 0, "sigmoid": 1, "sin": 2}
 
 
 class Operator(C.Structure):
@@ -194,7 +196,8 @@ def problem_tensors(inst, device="cuda") -> dict:
                 weight=t(inst.weight, torch.float64), rhs=t(inst.rhs, torch.float64),
                 mu=t(inst.mu, torch.float64), hw=t(inst.hw, torch.float64),
                 w=t(inst.w, torch.float64), b=t(inst.b, torch.float64),
-                kappa=float(inst.kappa), ksq=float(inst.ksq))
+                kappa=float(inst.kappa), ksq=float(inst.ksq),
+                activation=ACTIVATIONS[getattr(inst, "activation", "tanh")])
 
 
 def plan_instance(inst, device="cuda") -> Plan:
@@ -208,7 +211,8 @@ def rfm_assemble(plan: Plan, prob: dict, M=None, h=None):
     h = torch.empty(L.N, dtype=torch.float64, device=dev) if h is None else h
     P = Problem(x=prob["x"].data_ptr(), rowop=prob["rowop"].data_ptr(), weight=prob["weight"].data_ptr(),
                 rhs=prob["rhs"].data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(),
-                w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"])
+                w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"],
+                activation=prob.get("activation", 0))
     nb = _lib.rfm_assemble_ws_bytes(C.byref(L))
     ws = _ws(nb, dev)
     _check(_lib.rfm_assemble(C.byref(L), C.byref(P), _ptr(M), _ptr(h), _ptr(ws), nb, _stream()),
@@ -230,7 +234,8 @@ def rfm_assemble_low(plan: Plan, prob: dict, dtype=F32, M=None, h=None):
     h = torch.empty(L.N, dtype=torch.float64, device=dev) if h is None else h
     P = Problem(x=prob["x"].data_ptr(), rowop=prob["rowop"].data_ptr(), weight=prob["weight"].data_ptr(),
                 rhs=prob["rhs"].data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(),
-                w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"])
+                w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"],
+                activation=prob.get("activation", 0))
     nb = _lib.rfm_assemble_ws_bytes(C.byref(L))
     ws = _ws(nb, dev)
     _check(_lib.rfm_assemble_low(C.byref(L), C.byref(P), int(dtype), _ptr(M), _ptr(h), _ptr(ws), nb, _stream()),
@@ -260,7 +265,7 @@ def rfm_evaluate(tplan: Plan, xd, prob: dict, a, u_exact=None, ws=None):
     L = tplan.layout
     dev = xd.device
     P = Problem(x=xd.data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(), w=prob["w"].data_ptr(),
-                b=prob["b"].data_ptr())
+                b=prob["b"].data_ptr(), activation=prob.get("activation", 0))
     uhat = torch.empty(L.N, dtype=torch.float64, device=dev)
     nb = _lib.rfm_evaluate_ws_bytes(C.byref(L))
     if ws is None or ws.numel() < nb:

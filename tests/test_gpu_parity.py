@@ -24,6 +24,10 @@ pytestmark = pytest.mark.gpu
 
 U = np.finfo(np.float64).eps / 2
 TINY = ["poisson1d", "poisson2d", "heat3d", "helmholtz2d_uneven"]
+# every tiny instance with tanh features, and the sigmoid and sin ablations on each geometry
+ACT_CASES = [(n, "tanh") for n in TINY] + [("poisson1d", "sigmoid"), ("poisson2d", "sin"),
+                                           ("heat3d", "sin"), ("helmholtz2d_uneven", "sigmoid"),
+                                           ("poisson2d", "sigmoid"), ("poisson1d", "sin")]
 
 
 @pytest.fixture(scope="module")
@@ -44,10 +48,10 @@ def _setup(rfm, inst):
     return plan, prob
 
 
-@pytest.mark.parametrize("name", TINY)
-def test_assembly_matches_oracle(rfm, name):
-    inst = I.tiny(name)
-    print(f"[assembly] {name}", flush=True)
+@pytest.mark.parametrize("name,act", ACT_CASES)
+def test_assembly_matches_oracle(rfm, name, act):
+    inst = I.with_activation(I.tiny(name), act)
+    print(f"[assembly] {name} {act}", flush=True)
     plan, prob = _setup(rfm, inst)
     M, h = rfm.rfm_assemble(plan, prob)
     torch.cuda.synchronize()
@@ -275,11 +279,12 @@ def test_coefficients_match_oracle_back_substitution(rfm):
         assert np.all(ag[sl][a_or[sl] == 0.0] == 0.0)
 
 
-@pytest.mark.parametrize("name", ["poisson1d", "heat3d"])
-def test_end_to_end_gpu_pipeline(rfm, name):
+@pytest.mark.parametrize("name,act", [("poisson1d", "tanh"), ("heat3d", "tanh"),
+                                      ("poisson1d", "sigmoid"), ("poisson1d", "sin")])
+def test_end_to_end_gpu_pipeline(rfm, name, act):
     """Each side with its own factors: report the differences, check the error metric."""
-    inst = I.tiny(name) if name != "poisson1d" else I.workload("poisson1d")
-    print(f"[e2e] {name}", flush=True)
+    inst = I.with_activation(I.tiny(name) if name != "poisson1d" else I.workload("poisson1d"), act)
+    print(f"[e2e] {name} {act}", flush=True)
     plan, prob = _setup(rfm, inst)
     M, h = rfm.rfm_assemble(plan, prob)
     fact = rfm.rfm_rrqr_filter(plan, M, 1e-12)
@@ -636,14 +641,14 @@ def test_multi_rhs_warm_start_guard_per_column(rfm):
         assert iw[b] <= 2
 
 
-@pytest.mark.parametrize("name", TINY)
-def test_evaluation_and_l1_error_match_oracle(rfm, name):
+@pytest.mark.parametrize("name,act", ACT_CASES)
+def test_evaluation_and_l1_error_match_oracle(rfm, name, act):
     """u_hat at the test grid and e_L1 (Sec. 4.2) from the GPU against the oracle's
     evaluation of the same coefficients; u_hat within 64 u times the absolute-value
     evaluation sum_j w_j sum_k |a_jk| |phi_jk| (cancellation between features is the
     rule for these coefficients)."""
-    inst = I.tiny(name)
-    print(f"[evaluate] {name}", flush=True)
+    inst = I.with_activation(I.tiny(name), act)
+    print(f"[evaluate] {name} {act}", flush=True)
     rng = np.random.default_rng(21)
     a = rng.standard_normal(inst.feat_off[-1]) * 10.0 ** rng.uniform(-2, 3, inst.feat_off[-1])
     xt = inst.test_points(7 if inst.d == 3 else 12 if inst.d == 2 else 40)
@@ -665,7 +670,8 @@ def test_evaluation_and_l1_error_match_oracle(rfm, name):
         if r.size == 0:
             continue
         k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
-        phi, _, _ = assembly.features(xt[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1])
+        phi, _, _ = assembly.features(xt[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1],
+                                      inst.activation)
         W, _, _ = assembly.unnormalised_window(xt[r], inst.mu[j], inst.hw[j])
         scale[r] += (W / S[r]) * (np.abs(phi) @ np.abs(a[k0:k1]))
     err = np.abs(uh.cpu().numpy() - uo)
@@ -677,13 +683,13 @@ def test_evaluation_and_l1_error_match_oracle(rfm, name):
     assert e2 is None and torch.equal(uh2, uh)
 
 
-@pytest.mark.parametrize("name", TINY)
+@pytest.mark.parametrize("name,act", ACT_CASES)
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_low_precision_assembly_error_against_oracle(rfm, name, dtype):
+def test_low_precision_assembly_error_against_oracle(rfm, name, act, dtype):
     """The precision form's assembly (binary32 arithmetic, binary32 or bfloat16 storage):
     normwise relative error per block against the binary64 oracle, measured and reported;
     bounded by 1e-3 (binary32) and 1e-2 (bfloat16: its own rounding is 2^-9 relative)."""
-    inst = I.tiny(name)
+    inst = I.with_activation(I.tiny(name), act)
     plan, prob = _setup(rfm, inst)
     Ml, h = rfm.rfm_assemble_low(plan, prob, rfm.F32 if dtype == "f32" else rfm.BF16)
     M64, h64 = rfm.rfm_assemble(plan, prob)
@@ -699,6 +705,6 @@ def test_low_precision_assembly_error_against_oracle(rfm, name, dtype):
         if ref.size:
             rel.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     rel = np.array(rel)
-    print(f"[assembly {dtype}] {name}: normwise relative error per block max {rel.max():.2e}, "
+    print(f"[assembly {dtype}] {name} {act}: normwise relative error per block max {rel.max():.2e}, "
           f"median {np.median(rel):.2e}", flush=True)
     assert rel.max() <= (1e-3 if dtype == "f32" else 1e-2)

@@ -77,7 +77,15 @@ def test_window_factor_derivatives_finite_difference():
     assert f2c[0] == pytest.approx(-4 * np.pi**2 / sig**2, rel=1e-15)
 
 
-def test_feature_derivatives_finite_difference():
+# each activation through an expression other than the oracle's own: the sigmoid as
+# (1 + tanh(s/2)) / 2, sin as the imaginary part of exp(i s)
+_ACT_CLOSED = {"tanh": np.tanh,
+               "sigmoid": lambda s: 0.5 * (1.0 + np.tanh(0.5 * s)),
+               "sin": lambda s: np.exp(1j * s).imag}
+
+
+@pytest.mark.parametrize("act", assembly.ACTIVATIONS)
+def test_feature_derivatives_finite_difference(act):
     rng = np.random.default_rng(3)
     d = 3
     x = rng.uniform(0.2, 0.5, (9, d))
@@ -85,17 +93,35 @@ def test_feature_derivatives_finite_difference():
     hw = np.array([0.2, 0.25, 0.3])
     wk = rng.uniform(-1, 1, (5, d))
     bk = rng.uniform(-1, 1, 5)
-    phi, dphi, ddphi = assembly.features(x, mu, hw, wk, bk)
-    assert np.allclose(phi, np.tanh(((x - mu) / hw) @ wk.T + bk), rtol=0, atol=1e-15)
+    phi, dphi, ddphi = assembly.features(x, mu, hw, wk, bk, act)
+    assert np.allclose(phi, _ACT_CLOSED[act](((x - mu) / hw) @ wk.T + bk), rtol=0, atol=1e-15)
     e = 1e-5
     for i in range(d):
         xp, xm = x.copy(), x.copy()
         xp[:, i] += e
         xm[:, i] -= e
-        pp, _, _ = assembly.features(xp, mu, hw, wk, bk)
-        pm, _, _ = assembly.features(xm, mu, hw, wk, bk)
+        pp, _, _ = assembly.features(xp, mu, hw, wk, bk, act)
+        pm, _, _ = assembly.features(xm, mu, hw, wk, bk, act)
         assert np.allclose((pp - pm) / (2 * e), dphi[:, :, i], atol=1e-8)
         assert np.allclose((pp - 2 * phi + pm) / e**2, ddphi[:, :, i], atol=2e-4)
+
+
+def test_activation_special_values():
+    """Xi, Xi', Xi'' at 0 and far out: tanh (0, 1, 0), sigmoid (1/2, 1/4, 0), sin (0, 1, 0);
+    sigmoid and tanh saturate with vanishing derivatives; sin(pi/2) = 1, sin''(pi/2) = -1."""
+    z = np.array([0.0])
+    for act, want in (("tanh", (0.0, 1.0, 0.0)), ("sigmoid", (0.5, 0.25, 0.0)), ("sin", (0.0, 1.0, 0.0))):
+        got = assembly.activation(act, z)
+        assert [float(v[0]) for v in got] == list(want), act
+    for act, lim in (("tanh", 1.0), ("sigmoid", 1.0)):
+        t, g, gg = assembly.activation(act, np.array([40.0]))
+        assert t[0] == pytest.approx(lim, abs=1e-15) and abs(g[0]) < 1e-15 and abs(gg[0]) < 1e-15
+    t, g, gg = assembly.activation("sigmoid", np.array([-800.0]))  # exp overflows to inf
+    assert t[0] == 0.0 and g[0] == 0.0 and gg[0] == 0.0
+    t, g, gg = assembly.activation("sin", np.array([np.pi / 2]))
+    assert t[0] == 1.0 and abs(g[0]) < 1e-16 and gg[0] == -1.0
+    with pytest.raises(ValueError):
+        assembly.activation("relu", z)
 
 
 def _fd_operator(inst, a, xr, op):
@@ -122,9 +148,12 @@ def _fd_operator(inst, a, xr, op):
     return u0
 
 
-@pytest.mark.parametrize("name", ["poisson1d", "poisson2d", "heat3d", "helmholtz2d_uneven"])
-def test_assembled_rows_match_finite_difference_operator(name):
-    inst = I.tiny(name)
+@pytest.mark.parametrize("name,act", [("poisson1d", "tanh"), ("poisson2d", "tanh"), ("heat3d", "tanh"),
+                                      ("helmholtz2d_uneven", "tanh"), ("poisson1d", "sigmoid"),
+                                      ("poisson2d", "sin"), ("heat3d", "sigmoid"),
+                                      ("helmholtz2d_uneven", "sin")])
+def test_assembled_rows_match_finite_difference_operator(name, act):
+    inst = I.with_activation(I.tiny(name), act)
     rows, blocks, h = assembly.assemble(inst)
     M = assembly.global_dense(inst, rows, blocks)
     rng = np.random.default_rng(7)
@@ -170,13 +199,16 @@ def test_incidence_strict_support_and_cover_bound():
     assert cover.max() <= 2 ** inst.d     # overlap fraction < 1/2
 
 
-@pytest.mark.parametrize("name", ["poisson1d", "heat3d", "helmholtz2d_uneven"])
-def test_entry_error_scale_bounds_binary64_rounding(name):
+@pytest.mark.parametrize("name,act", [("poisson1d", "tanh"), ("heat3d", "tanh"),
+                                      ("helmholtz2d_uneven", "tanh"), ("poisson1d", "sigmoid"),
+                                      ("heat3d", "sin"), ("helmholtz2d_uneven", "sigmoid"),
+                                      ("poisson2d", "sin")])
+def test_entry_error_scale_bounds_binary64_rounding(name, act):
     """The binary64 assembly sits within a few u * E of an extended-precision evaluation,
     E the absolute-value evaluation used to size the GPU/oracle tolerance."""
-    inst = I.tiny(name)
+    inst = I.with_activation(I.tiny(name), act)
     rows, blocks, _ = assembly.assemble(inst)
-    ext = I.tiny(name)
+    ext = I.with_activation(I.tiny(name), act)
     for k in ("x", "mu", "hw", "w", "b", "weight", "rhs"):
         setattr(ext, k, getattr(inst, k).astype(np.longdouble))
     _, blocks_ext, _ = assembly.assemble(ext)
