@@ -51,12 +51,19 @@ typedef enum {
 } rfm_dtype;
 
 /* Row operators (the linear PDE / boundary operators N and B_l of Section 2.1).
- * Inputs x have d coordinates; for RFM_OP_HEAT the last coordinate is time. */
+ * Inputs x have d coordinates; for RFM_OP_HEAT the last coordinate is time.
+ * RFM_OP_COEF + i applies operator i of the problem's coefficient table (opcoef):
+ *   c0 u + sum_i (c1_i d_i u + c2_i d_ii u),
+ * which covers the paper's own problems (Section 5.1): the damped oscillator
+ * m u'' + mu u' + k u and its initial velocity u'(0), and the wave operator
+ * sum_{i<d-1} d_ii u - c^-2 d_tt u.  A code that is none of these, or a table index out of
+ * range, is read as RFM_OP_VALUE. */
 typedef enum {
   RFM_OP_NEG_LAPLACE = 0, /* -sum_i d_ii u                          */
   RFM_OP_HEAT = 1,        /* d_t u - kappa * sum_{i<d-1} d_ii u       */
   RFM_OP_HELMHOLTZ = 2,   /* sum_i d_ii u + ksq * u                   */
-  RFM_OP_VALUE = 3        /* u (Dirichlet and initial-condition rows)  */
+  RFM_OP_VALUE = 3,       /* u (Dirichlet and initial-condition rows)  */
+  RFM_OP_COEF = 16        /* + i: constant-coefficient operator i of opcoef */
 } rfm_rowop;
 
 /* Block layout of the global matrix (eq. DomainDecomp).  Produced on the host by
@@ -98,7 +105,11 @@ typedef enum {
 
 /* Discretised problem (Section 2.1 and Section 4.2): subdomain geometry, random
  * features phi_jk = act(w_jk . (x - mu_j)/hw_j + b_jk) (eq. fcn_depth_h, depth 1,
- * inputs normalised to [-1,1] per subdomain), points and per-row data. */
+ * inputs normalised to [-1,1] per subdomain), points and per-row data.
+ * A hard-constraint ansatz (Section 5.1: u~ = g u_hat, after Lagaris et al.) is given by its
+ * factor g per point: ansatz [N*(1+2d)] holds, for point r, g, d_i g (i < d) and d_ii g
+ * (i < d) at offset r*(1+2d); the row operators then apply to g u_hat (product rule), and
+ * rfm_evaluate returns g u_hat.  An additive part of an ansatz belongs in rhs. */
 typedef struct {
   const double *x;        /* device [N*d] row-major points                 */
   const int32_t *rowop;   /* device [N] rfm_rowop per row                  */
@@ -111,6 +122,10 @@ typedef struct {
   double kappa;           /* RFM_OP_HEAT diffusion constant                */
   double ksq;             /* RFM_OP_HELMHOLTZ k^2                          */
   int32_t activation;     /* rfm_activation of the features (0 = tanh)     */
+  int32_t nopcoef;        /* rows of opcoef (0: no table)                  */
+  const double *opcoef;   /* device [nopcoef*(1+2d)]: per operator c0, c1_0..c1_{d-1},
+                             c2_0..c2_{d-1}; nullable when nopcoef = 0      */
+  const double *ansatz;   /* device [N*(1+2d)] g, d_i g, d_ii g per point, or NULL (g = 1) */
 } rfm_problem;
 
 /* Planning (sync, host only).  Builds the supports I_j of eq. DomainDecomp from host
@@ -356,11 +371,13 @@ size_t rfm_evaluate_ws_bytes(const rfm_layout *L);
 
 /* Solution at test points and its error (Sec. 4.2 performance evaluation; eq. elm_solution
  * with the windows of eq. used_window_function_nd): u_hat(x_t) = sum over the subdomains j
- * covering x_t (strict |x - mu| < hw) of w_j(x_t) sum_k a_(j,k) tanh(w_(j,k) . (x_t - mu_j)/hw_j
- * + b_(j,k)), and, with u_exact, e_L1 = mean_t |u_hat - u| / std(u) (population standard
- * deviation over the test points).  Lt: a layout planned (rfm_plan) on the test points with
- * the same subdomains and feature counts; P: its x = test points [T*d] (device), mu, hw, w, b
- * as for the assembly (the other fields are not read).  a device [ncols] (rfm_coefficients);
+ * covering x_t (strict |x - mu| < hw) of w_j(x_t) sum_k a_(j,k) Xi(w_(j,k) . (x_t - mu_j)/hw_j
+ * + b_(j,k)), times the ansatz factor g(x_t) when P->ansatz is set, and, with u_exact,
+ * e_L1 = mean_t |u_hat - u| / std(u) (population standard deviation over the test points).
+ * Lt: a layout planned (rfm_plan) on the test points with the same subdomains and feature
+ * counts; P: its x = test points [T*d] (device), mu, hw, w, b, activation as for the assembly,
+ * ansatz (nullable) per test point in the assembly's layout, of which only g is read (the
+ * other fields are not read).  a device [ncols] (rfm_coefficients);
  * uhat device [T]; u_exact device [T] and e_l1 host [1], both nullable together.  Sync when
  * e_l1 is requested.  ws: rfm_evaluate_ws_bytes(Lt). */
 rfm_status rfm_evaluate(const rfm_layout *Lt, const rfm_problem *P, const double *a, double *uhat,

@@ -12,7 +12,9 @@ Follows the paper's statement of the discretised problem:
   what_j = prod_d (1 + cos(pi (x_d - mu_jd) / sigma_jd))^2 on |x_d - mu_jd| < sigma_jd
   (eq. used_window_function_nd, with the parenthesis read as (x - mu)/sigma)
 * row r of M for column (j,k): s_r * Op_r[w_j phi_jk](x_r); h_r = s_r * rhs_r
-  (eq. ELMFBPINN_ls and the component-wise definition of N and B)
+  (eq. ELMFBPINN_ls and the component-wise definition of N and B); with a
+  hard-constraint trial solution u~ = g u_hat (Section 5.1) the operator acts on
+  g w_j phi_jk, still linear in the coefficients
 * I_j = rows where w_j(x_r) != 0, blocks M_j = M|_{I_j x K_j}  (eq. DomainDecomp)
 
 Derivatives are written out by hand (chain, product and quotient rules); the
@@ -24,6 +26,7 @@ from __future__ import annotations
 import numpy as np
 
 OP_NEG_LAPLACE, OP_HEAT, OP_HELMHOLTZ, OP_VALUE = 0, 1, 2, 3
+OP_COEF = 16   # + i: constant-coefficient operator i, c0 u + sum_a (c1_a d_a u + c2_a d_aa u)
 
 
 def support_mask(x: np.ndarray, mu_j: np.ndarray, hw_j: np.ndarray) -> np.ndarray:
@@ -137,7 +140,20 @@ def features(x: np.ndarray, mu_j, hw_j, wk: np.ndarray, bk: np.ndarray, act: str
     return t, dphi, ddphi
 
 
-def apply_rowop(op: np.ndarray, psi, dpsi, ddpsi, kappa: float, ksq: float):
+def _coef_rows(op: np.ndarray, opcoef, d: int):
+    """Per-row coefficients (c0 [m], c1 [m,d], c2 [m,d]) of the OP_COEF rows (zero elsewhere)
+    and the mask of rows that use them; codes past the table read as OP_VALUE."""
+    m = len(op)
+    c0, c1, c2 = np.zeros(m), np.zeros((m, d)), np.zeros((m, d))
+    nop = 0 if opcoef is None else len(opcoef)
+    use = (op >= OP_COEF) & (op - OP_COEF < nop)
+    for r in np.nonzero(use)[0]:
+        row = opcoef[op[r] - OP_COEF]
+        c0[r], c1[r], c2[r] = row[0], row[1:1 + d], row[1 + d:1 + 2 * d]
+    return c0, c1, c2, use
+
+
+def apply_rowop(op: np.ndarray, psi, dpsi, ddpsi, kappa: float, ksq: float, opcoef=None):
     """Row operator applied to psi = w phi given its derivatives ([m,K], [m,K,d], [m,K,d])."""
     d = dpsi.shape[2]
     lap = ddpsi.sum(axis=2)
@@ -150,7 +166,20 @@ def apply_rowop(op: np.ndarray, psi, dpsi, ddpsi, kappa: float, ksq: float):
     out = np.where(o == OP_HEAT, dpsi[:, :, d - 1] - kappa * spatial, out)
     out = np.where(o == OP_HELMHOLTZ, lap + ksq * psi, out)
     out = np.where(o == OP_VALUE, psi, out)
+    c0, c1, c2, use = _coef_rows(op, opcoef, d)
+    gen = (c0[:, None] * psi + np.einsum("ma,mka->mk", c1, dpsi) + np.einsum("ma,mka->mk", c2, ddpsi))
+    out = np.where(use[:, None], gen, out)
+    out = np.where((o >= OP_COEF) & ~use[:, None], psi, out)
     return out
+
+
+def with_ansatz(g, psi, dpsi, ddpsi):
+    """Product rule for g * psi, g given per row as [m, 1+2d] (g, d_a g, d_aa g)."""
+    d = dpsi.shape[2]
+    g0, g1, g2 = g[:, 0], g[:, 1:1 + d], g[:, 1 + d:1 + 2 * d]
+    return (g0[:, None] * psi,
+            g1[:, None, :] * psi[:, :, None] + g0[:, None, None] * dpsi,
+            g2[:, None, :] * psi[:, :, None] + 2.0 * g1[:, None, :] * dpsi + g0[:, None, None] * ddpsi)
 
 
 def assemble(inst):
@@ -162,6 +191,7 @@ def assemble(inst):
     """
     rows = incidence(inst)
     wins = windows(inst, rows)
+    G = None if inst.ansatz is None else np.asarray(inst.ansatz(inst.x), dtype=np.float64)
     blocks = []
     for j in range(inst.J):
         r = rows[j]
@@ -174,7 +204,9 @@ def assemble(inst):
         dpsi = dw[:, None, :] * phi[:, :, None] + w[:, None, None] * dphi
         ddpsi = (ddw[:, None, :] * phi[:, :, None] + 2.0 * dw[:, None, :] * dphi
                  + w[:, None, None] * ddphi)
-        Mj = apply_rowop(inst.rowop[r], psi, dpsi, ddpsi, inst.kappa, inst.ksq)
+        if G is not None:
+            psi, dpsi, ddpsi = with_ansatz(G[r], psi, dpsi, ddpsi)
+        Mj = apply_rowop(inst.rowop[r], psi, dpsi, ddpsi, inst.kappa, inst.ksq, inst.opcoef)
         blocks.append(inst.weight[r][:, None] * Mj)
     h = inst.weight * inst.rhs
     return rows, blocks, h
@@ -241,12 +273,18 @@ def entry_error_scale(inst, rows, j):
     psia = wa[:, None] * ta
     dpsia = dwa[:, None, :] * ta[:, :, None] + wa[:, None, None] * dphia
     ddpsia = ddwa[:, None, :] * ta[:, :, None] + 2.0 * dwa[:, None, :] * dphia + wa[:, None, None] * ddphia
+    if inst.ansatz is not None:
+        psia, dpsia, ddpsia = with_ansatz(np.abs(inst.ansatz(inst.x[r])), psia, dpsia, ddpsia)
     lap = ddpsia.sum(axis=2)
-    op = inst.rowop[r][:, None]
-    out = np.where(op == OP_NEG_LAPLACE, lap, psia)
+    op = inst.rowop[r]
+    out = np.where(op[:, None] == OP_NEG_LAPLACE, lap, psia)
     spatial = ddpsia[:, :, : d - 1].sum(axis=2) if d > 1 else np.zeros_like(psia)
-    out = np.where(op == OP_HEAT, dpsia[:, :, d - 1] + abs(inst.kappa) * spatial, out)
-    out = np.where(op == OP_HELMHOLTZ, lap + abs(inst.ksq) * psia, out)
+    out = np.where(op[:, None] == OP_HEAT, dpsia[:, :, d - 1] + abs(inst.kappa) * spatial, out)
+    out = np.where(op[:, None] == OP_HELMHOLTZ, lap + abs(inst.ksq) * psia, out)
+    c0, c1, c2, use = _coef_rows(op, inst.opcoef, d)
+    gen = (np.abs(c0)[:, None] * psia + np.einsum("ma,mka->mk", np.abs(c1), dpsia)
+           + np.einsum("ma,mka->mk", np.abs(c2), ddpsia))
+    out = np.where(use[:, None], gen, out)
     return np.abs(inst.weight[r])[:, None] * out
 
 

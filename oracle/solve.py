@@ -42,7 +42,8 @@ def coefficients(inst, facts, y: np.ndarray) -> np.ndarray:
 
 
 def evaluate(inst, a: np.ndarray, xt: np.ndarray) -> np.ndarray:
-    """u_hat at points xt for coefficients a (eq. elm_solution)."""
+    """u_hat at points xt for coefficients a (eq. elm_solution), times the hard-constraint
+    factor g when the instance has one (Section 5.1)."""
     N, d = xt.shape
     rows = [np.nonzero(assembly.support_mask(xt, inst.mu[j], inst.hw[j]))[0] for j in range(inst.J)]
     S = np.zeros(N)
@@ -60,6 +61,8 @@ def evaluate(inst, a: np.ndarray, xt: np.ndarray) -> np.ndarray:
         phi, _, _ = assembly.features(xt[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1],
                                       inst.activation)
         u[r] += (what[j] / S[r]) * (phi @ a[k0:k1])
+    if inst.ansatz is not None:
+        u = u * np.asarray(inst.ansatz(xt))[:, 0]   # u~ = g u_hat
     return u
 
 

@@ -4,7 +4,9 @@
 //   ascending j, accumulates the unnormalised windows what_j and their first and pure
 //   second derivatives, then writes the normalised window w_j = what_j / sum_i what_i
 //   and its derivatives (quotient rule) for every incidence (j, r) -- the partition of
-//   unity of eq. used_window_function_nd -- and h_r = s_r rhs_r (eq. ELMFBPINN_ls).
+//   unity of eq. used_window_function_nd -- and h_r = s_r rhs_r (eq. ELMFBPINN_ls).  A
+//   hard-constraint ansatz factor g is folded in here: the table holds g w_j and its
+//   derivatives, so the entries below see the product g w_j phi_jk unchanged.
 // assemble_entries: lane <-> row of one block, so the column-major block is written
 //   with coalesced 64-wide stores; each thread produces a run of features for its row,
 //   reusing the row's point and window data.  Entry = s_r Op_r[w_j phi_jk](x_r) by the
@@ -78,6 +80,19 @@ __global__ __launch_bounds__(256) void window_table(rfm_layout L, rfm_problem P,
       ddS[i] += ddW[i];
     }
   }
+  // ansatz factor: g, d_i g, d_ii g (g = 1 without one)
+  Tc g = (Tc)1, dg[D], ddg[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) dg[i] = ddg[i] = 0;
+  if (P.ansatz) {
+    const double *ar = P.ansatz + r * (1 + 2 * D);
+    g = (Tc)ar[0];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      dg[i] = (Tc)ar[1 + i];
+      ddg[i] = (Tc)ar[1 + D + i];
+    }
+  }
   for (int64_t q = q0; q < q1; ++q) {
     const int64_t p = L.rinc[q];
     const int32_t j = L.inc_blk[p];
@@ -85,12 +100,23 @@ __global__ __launch_bounds__(256) void window_table(rfm_layout L, rfm_problem P,
     window_factors<D, Tc>(xr, P.mu + (int64_t)j * D, P.hw + (int64_t)j * D, W, dW, ddW);
     const Tc w = W / S;
     Tc *out = win + p * (1 + 2 * D);
-    out[0] = w;
+    if (!P.ansatz) {
+      out[0] = w;
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const Tc dw = (dW[i] - w * dS[i]) / S;
-      out[1 + i] = dw;
-      out[1 + D + i] = (ddW[i] - (Tc)2 * dw * dS[i] - w * ddS[i]) / S;
+      for (int i = 0; i < D; ++i) {
+        const Tc dw = (dW[i] - w * dS[i]) / S;
+        out[1 + i] = dw;
+        out[1 + D + i] = (ddW[i] - (Tc)2 * dw * dS[i] - w * ddS[i]) / S;
+      }
+    } else {
+      out[0] = g * w;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const Tc dw = (dW[i] - w * dS[i]) / S;
+        const Tc ddw = (ddW[i] - (Tc)2 * dw * dS[i] - w * ddS[i]) / S;
+        out[1 + i] = dg[i] * w + g * dw;
+        out[1 + D + i] = ddg[i] * w + (Tc)2 * dg[i] * dw + g * ddw;
+      }
     }
   }
 }
@@ -136,9 +162,27 @@ __global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, 
     dw[a] = wp[1 + a];
     ddw[a] = wp[1 + D + a];
   }
-  const int op = P.rowop[r];
+  int op = P.rowop[r];
   const Tc sr = (Tc)P.weight[r];
   const Tc kappa = (Tc)P.kappa, ksq = (Tc)P.ksq;
+  // constant-coefficient operator of the table: c0 u + sum_a (c1_a d_a u + c2_a d_aa u)
+  Tc c0 = 0, c1[D], c2[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) c1[a] = c2[a] = 0;
+  if (op >= RFM_OP_COEF) {
+    const int t = op - RFM_OP_COEF;
+    if (t < P.nopcoef) {
+      const double *cr = P.opcoef + (int64_t)t * (1 + 2 * D);
+      c0 = (Tc)cr[0];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        c1[a] = (Tc)cr[1 + a];
+        c2[a] = (Tc)cr[1 + D + a];
+      }
+    } else {
+      op = RFM_OP_VALUE;
+    }
+  }
   To *out = M + L.blk_off[j] + (int64_t)i;
   const int k1 = min(K, k0 + kFeatPerThread);
   for (int k = k0; k < k1; ++k) {
@@ -150,7 +194,7 @@ __global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, 
     Tc t, g, gg;  // phi, phi', phi'' of the activation at s
     activation3<Tc>(P.activation, s, t, g, gg);
     const Tc psi = w * t;
-    Tc lap = 0, spatial = 0, dlast = 0;
+    Tc lap = 0, spatial = 0, dlast = 0, gen = c0 * psi;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const Tc sc = (Tc)wk[a] / hwj[a];
@@ -161,13 +205,14 @@ __global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, 
       lap += ddpsi;
       if (a < D - 1) spatial += ddpsi;
       if (a == D - 1) dlast = dpsi;
+      gen += c1[a] * dpsi + c2[a] * ddpsi;
     }
     Tc v;
     switch (op) {
       case RFM_OP_NEG_LAPLACE: v = -lap; break;
       case RFM_OP_HEAT: v = dlast - kappa * (D > 1 ? spatial : (Tc)0); break;
       case RFM_OP_HELMHOLTZ: v = lap + ksq * psi; break;
-      default: v = psi; break;
+      default: v = (op >= RFM_OP_COEF) ? gen : psi; break;
     }
     out[(int64_t)k * m] = Out<To>::put(sr * v);
   }
@@ -201,6 +246,10 @@ rfm_status check_problem(const rfm_layout *L, const rfm_problem *P, const void *
   if (s != RFM_OK) return s;
   if (!P || !P->x || !P->rowop || !P->weight || !P->rhs || !P->mu || !P->hw || !P->w || !P->b)
     return fail(RFM_EINVAL, std::string(who) + ": null problem array");
+  if (P->nopcoef < 0 || (P->nopcoef > 0 && !P->opcoef))
+    return fail(RFM_EINVAL, std::string(who) + ": operator table size or pointer");
+  if (P->activation < RFM_ACT_TANH || P->activation > RFM_ACT_SIN)
+    return fail(RFM_EINVAL, std::string(who) + ": unknown activation");
   if (!h || (L->nnz > 0 && !M)) return fail(RFM_EINVAL, std::string(who) + ": null output");
   if (ws_bytes < rfm_assemble_ws_bytes(L) || (rfm_assemble_ws_bytes(L) > 0 && !ws))
     return fail(RFM_EINVAL, std::string(who) + ": workspace too small");

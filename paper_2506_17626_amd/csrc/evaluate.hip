@@ -1,7 +1,8 @@
 // Evaluation of the solution at test points and its L1 error (Sec. 4.2 performance
 // evaluation): u_hat(x) = sum over the subdomains j covering x of w_j(x) phi_j(x)^T a_j
 // (eq. elm_solution with the partition-of-unity windows of eq. used_window_function_nd),
-// and e_L1 = mean |u_hat - u| / std(u).
+// times a hard-constraint ansatz factor g(x) when the problem has one (Section 5.1), and
+// e_L1 = mean |u_hat - u| / std(u).
 //
 // eval_points: one thread per test point; the covering subdomains in ascending j (the
 //   transpose incidence of the test-point layout), the normaliser first, then the window-
@@ -65,6 +66,7 @@ __global__ __launch_bounds__(kEvalThreads) void eval_points(rfm_layout L, rfm_pr
       }
       u += w * acc;
     }
+    if (P.ansatz) u *= P.ansatz[r * (1 + 2 * D)];
     uhat[r] = u;
     if (ue) {
       uv = ue[r];
@@ -133,6 +135,8 @@ extern "C" rfm_status rfm_evaluate(const rfm_layout *L, const rfm_problem *P, co
   if (!P || !P->x || !P->mu || !P->hw || !P->w || !P->b || !a || !uhat)
     return fail(RFM_EINVAL, "rfm_evaluate: null pointer");
   if ((u_exact || e_l1) && (!u_exact || !e_l1)) return fail(RFM_EINVAL, "rfm_evaluate: u_exact and e_l1 go together");
+  if (P->activation < RFM_ACT_TANH || P->activation > RFM_ACT_SIN)
+    return fail(RFM_EINVAL, "rfm_evaluate: unknown activation");
   if (!ws || ws_bytes < rfm_evaluate_ws_bytes(L)) return fail(RFM_EINVAL, "rfm_evaluate: workspace too small");
   hipStream_t st = (hipStream_t)stream;
   double *sums = (double *)ws, *part = sums + 4;

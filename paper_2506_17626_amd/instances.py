@@ -3,9 +3,11 @@
 This module only draws and lays out *inputs*: subdomain centres and
 half-widths, random feature parameters, collocation points, per-row operator
 ids, row weights and right-hand-side values, plus the manufactured exact
-solution used to measure the error of a solve.  It holds none of the method's
-arithmetic (no window, feature or operator evaluation, no factorisation, no
-solver): both the CPU oracle and the HIP path consume the arrays it returns.
+solution used to measure the error of a solve, and, for the paper's own problems,
+the operator coefficients and the hard-constraint factor of the trial solution
+(problem data, like the forcing).  It holds none of the method's arithmetic (no
+window, feature or operator evaluation, no factorisation, no solver): both the
+CPU oracle and the HIP path consume the arrays it returns.
 
 Problem statement: a linear PDE with linear boundary operators (paper,
 Section 2.1), discretised by a regular overlapping decomposition (Section 4.2,
@@ -40,6 +42,7 @@ OP_NEG_LAPLACE = 0   # -sum_i d_ii
 OP_HEAT = 1          # d_t - kappa * sum_{spatial i} d_ii  (time is the last input dim)
 OP_HELMHOLTZ = 2     # sum_i d_ii + k^2
 OP_VALUE = 3         # identity (Dirichlet / initial-condition rows)
+OP_COEF = 16         # + i: c0 + sum_i (c1_i d_i + c2_i d_ii), row i of Instance.opcoef
 
 
 class Rng:
@@ -92,6 +95,8 @@ class Instance:
     test_grid: int = 0      # points per dim of the cell-centred test grid
     meta: dict = field(default_factory=dict)
     activation: str = "tanh"  # feature activation: "tanh", "sigmoid" or "sin"
+    opcoef: np.ndarray | None = None  # [nop, 1+2d] c0, c1_i, c2_i of the OP_COEF + i rows
+    ansatz: object = None   # callable x[n,d] -> [n, 1+2d]: g, d_i g, d_ii g of u~ = g u_hat
 
     @property
     def N(self) -> int:
@@ -135,6 +140,22 @@ def _features(rng: Rng, K: np.ndarray, d: int):
     w = rng.uniform(-1.0, 1.0, total * d).reshape(total, d)
     b = rng.uniform(-1.0, 1.0, total)
     return feat_off, w, b
+
+
+def _paper_geometry(d: int, S: int, delta: float):
+    """eq. dd on [0,1]^d: centres (j-1)/(S-1) per dim, half-width delta / (2 (S-1))."""
+    centres_1d = np.arange(S) / (S - 1)
+    idx = np.stack(np.meshgrid(*([np.arange(S)] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    mu = centres_1d[idx]
+    hw = np.full_like(mu, delta / (2.0 * (S - 1)))
+    return mu, hw
+
+
+def _full_grid(d: int, n: int) -> np.ndarray:
+    """Regular grid of n points per dim over [0,1]^d, end points included (Section 5,
+    interior collocation points)."""
+    g = np.linspace(0.0, 1.0, n)
+    return np.stack(np.meshgrid(*([g] * d), indexing="ij"), axis=-1).reshape(-1, d)
 
 
 def _face_grid(n: int) -> np.ndarray:
@@ -316,6 +337,83 @@ def poisson2d_family_exact(params_row: np.ndarray):
 
 
 # ---------------------------------------------------------------- named workloads
+def oscillator1d(S=20, K=8, omega0=60.0, mu_f=4.0, m=1.0, delta=2.9, seed=0,
+                 name="oscillator1d") -> Instance:
+    """Damped harmonic oscillator (Section 5.1): m u'' + mu u' + k u = 0 on [0,1] with
+    k = m omega0^2, u(0) = 1, u'(0) = 0, under-damped (mu / 2m < omega0).  Exact solution
+    u = e^{-dt} cos(w t + p) / cos p with d = mu / 2m, w = sqrt(omega0^2 - d^2) and
+    tan p = -d / w.  Interior points: S K on the regular grid; two boundary sets of one row
+    each (the value and the velocity at t = 0); test points 50 S."""
+    d = 1
+    rng = Rng(seed)
+    mu, hw = _paper_geometry(d, S, delta)
+    feat_off, w, b = _features(rng, np.full(S, K, dtype=np.int64), d)
+    k = m * omega0**2
+    dmp = mu_f / (2.0 * m)
+    om = math.sqrt(omega0**2 - dmp**2)
+    ph = math.atan(-dmp / om)
+
+    def exact(x):
+        t = x[:, 0]
+        return np.exp(-dmp * t) * np.cos(om * t + ph) / math.cos(ph)
+
+    xi = _full_grid(d, S * math.ceil(K))
+    xb = np.zeros((2, 1))
+    NI = xi.shape[0]
+    x = np.concatenate([xi, xb])
+    rowop = np.concatenate([np.full(NI, OP_COEF + 0), [OP_VALUE, OP_COEF + 1]]).astype(np.int32)
+    weight = np.concatenate([np.full(NI, 1 / math.sqrt(NI)), [1.0, 1.0]])
+    rhs = np.concatenate([np.zeros(NI), [1.0, 0.0]])
+    opcoef = np.array([[k, mu_f, m],      # m u'' + mu u' + k u
+                       [0.0, 1.0, 0.0]])  # u'
+    return Instance(name, d, S, mu, hw, feat_off, w, b, x, rowop, weight, rhs, exact=exact,
+                    test_grid=50 * S, opcoef=opcoef,
+                    meta=dict(S=S, K=K, omega0=omega0, mu=mu_f, m=m, delta=delta, seed=seed))
+
+
+def _box_factor(a: float, x: np.ndarray):
+    """F(x) = tanh(a x) tanh(a (1 - x)) and its first two derivatives."""
+    p, q = np.tanh(a * x), np.tanh(a * (1.0 - x))
+    p1, q1 = a * (1.0 - p * p), -a * (1.0 - q * q)
+    p2, q2 = -2.0 * a * p * p1, 2.0 * a * q * q1
+    return p * q, p1 * q + p * q1, p2 * q + 2.0 * p1 * q1 + p * q2
+
+
+def laplace2d_multiscale(S=16, K=16, n=3, delta=2.9, seed=0, name="laplace2d_multiscale") -> Instance:
+    """Multi-scale Laplacian (Section 5.1): -Laplace u = f on [0,1]^2, u = 0 on the boundary,
+    u = (1/n) sum_{i<=n} sin(w_i pi x) sin(w_i pi y) with w_i = 2^i, f = -Laplace u.  The
+    boundary condition is imposed by the hard-constraint trial solution u~ = g u_hat with
+    g = F(x) F(y), F(s) = tanh(w_n s) tanh(w_n (1 - s)), so every row is a PDE row
+    ((S ceil(sqrt K))^2 of them on the regular grid); test points 6 S per dim."""
+    d = 2
+    rng = Rng(seed)
+    mu, hw = _paper_geometry(d, S, delta)
+    feat_off, w, b = _features(rng, np.full(S * S, K, dtype=np.int64), d)
+    om = 2.0 ** np.arange(1, n + 1)
+
+    def exact(x):
+        return np.mean([np.sin(o * np.pi * x[:, 0]) * np.sin(o * np.pi * x[:, 1]) for o in om], axis=0)
+
+    def forcing(x):
+        return np.mean([2 * (o * np.pi) ** 2 * np.sin(o * np.pi * x[:, 0]) * np.sin(o * np.pi * x[:, 1])
+                        for o in om], axis=0)
+
+    a = float(om[-1])
+
+    def ansatz(x):
+        F0, F0d, F0dd = _box_factor(a, x[:, 0])
+        F1, F1d, F1dd = _box_factor(a, x[:, 1])
+        return np.stack([F0 * F1, F0d * F1, F0 * F1d, F0dd * F1, F0 * F1dd], axis=1)
+
+    xi = _full_grid(d, S * math.ceil(math.sqrt(K)))
+    NI = xi.shape[0]
+    rowop = np.full(NI, OP_NEG_LAPLACE, dtype=np.int32)
+    weight = np.full(NI, 1 / math.sqrt(NI))
+    return Instance(name, d, S * S, mu, hw, feat_off, w, b, xi, rowop, weight, forcing(xi),
+                    exact=exact, test_grid=6 * S, ansatz=ansatz,
+                    meta=dict(S=S, K=K, n=n, delta=delta, seed=seed))
+
+
 def workload(name: str, seed: int = 0) -> Instance:
     """The five named workloads at their full sizes."""
     if name == "poisson1d":       # 20 subdomains, 64 features, 100 points each
@@ -328,6 +426,10 @@ def workload(name: str, seed: int = 0) -> Instance:
         return helmholtz2d_uneven(seed=seed)
     if name == "poisson2d_family":    # geometry of poisson2d; RHS from poisson2d_family_rhs
         return poisson2d(seed=seed, name="poisson2d_family")
+    if name == "oscillator1d":        # the paper's oscillator baseline: S=20, K=8, omega0=60
+        return oscillator1d(seed=seed)
+    if name == "laplace2d_multiscale":  # the paper's Laplacian baseline: S=16, K=16, n=3
+        return laplace2d_multiscale(seed=seed)
     raise KeyError(name)
 
 
@@ -349,4 +451,8 @@ def tiny(name: str, seed: int = 0) -> Instance:
         return heat3d(S=2, K=48, n=5, nb=10, seed=seed, name="heat3d_tiny")
     if name == "helmholtz2d_uneven":
         return helmholtz2d_uneven(S=4, Klo=20, Khi=70, clo=20, chi=90, seed=seed, name="helmholtz2d_uneven_tiny")
+    if name == "oscillator1d":
+        return oscillator1d(S=6, K=8, omega0=15.0, seed=seed, name="oscillator1d_tiny")
+    if name == "laplace2d_multiscale":
+        return laplace2d_multiscale(S=4, K=9, n=2, seed=seed, name="laplace2d_multiscale_tiny")
     raise KeyError(name)

@@ -40,7 +40,8 @@ class Layout(C.Structure):
 
 class Problem(C.Structure):
     _fields_ = [("x", _p), ("rowop", _p), ("weight", _p), ("rhs", _p), ("mu", _p), ("hw", _p),
-                ("w", _p), ("b", _p), ("kappa", C.c_double), ("ksq", C.c_double), ("activation", C.c_int32)]
+                ("w", _p), ("b", _p), ("kappa", C.c_double), ("ksq", C.c_double), ("activation", C.c_int32),
+                ("nopcoef", C.c_int32), ("opcoef", _p), ("ansatz", _p)]
 
 ACTIVATIONS = {"tanh": 0, "sigmoid": 1, "sin": 2}
 
@@ -197,7 +198,20 @@ def problem_tensors(inst, device="cuda") -> dict:
                 mu=t(inst.mu, torch.float64), hw=t(inst.hw, torch.float64),
                 w=t(inst.w, torch.float64), b=t(inst.b, torch.float64),
                 kappa=float(inst.kappa), ksq=float(inst.ksq),
-                activation=ACTIVATIONS[getattr(inst, "activation", "tanh")])
+                activation=ACTIVATIONS[inst.activation],
+                opcoef=None if inst.opcoef is None else t(inst.opcoef, torch.float64),
+                ansatz=None if inst.ansatz is None else t(inst.ansatz(inst.x), torch.float64))
+
+
+def _problem(prob: dict) -> Problem:
+    """C struct of a problem_tensors dict (pointers into its device tensors)."""
+    oc = prob.get("opcoef")
+    an = prob.get("ansatz")
+    return Problem(x=prob["x"].data_ptr(), rowop=prob["rowop"].data_ptr(), weight=prob["weight"].data_ptr(),
+                   rhs=prob["rhs"].data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(),
+                   w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"],
+                   activation=prob.get("activation", 0), nopcoef=0 if oc is None else oc.shape[0],
+                   opcoef=_ptr(oc), ansatz=_ptr(an))
 
 
 def plan_instance(inst, device="cuda") -> Plan:
@@ -209,10 +223,7 @@ def rfm_assemble(plan: Plan, prob: dict, M=None, h=None):
     dev = prob["x"].device
     M = torch.empty(max(L.nnz, 1), dtype=torch.float64, device=dev) if M is None else M
     h = torch.empty(L.N, dtype=torch.float64, device=dev) if h is None else h
-    P = Problem(x=prob["x"].data_ptr(), rowop=prob["rowop"].data_ptr(), weight=prob["weight"].data_ptr(),
-                rhs=prob["rhs"].data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(),
-                w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"],
-                activation=prob.get("activation", 0))
+    P = _problem(prob)
     nb = _lib.rfm_assemble_ws_bytes(C.byref(L))
     ws = _ws(nb, dev)
     _check(_lib.rfm_assemble(C.byref(L), C.byref(P), _ptr(M), _ptr(h), _ptr(ws), nb, _stream()),
@@ -232,10 +243,7 @@ def rfm_assemble_low(plan: Plan, prob: dict, dtype=F32, M=None, h=None):
     tdt = {F32: torch.float32, BF16: torch.bfloat16}[dtype]
     M = torch.empty(max(L.nnz, 1), dtype=tdt, device=dev) if M is None else M
     h = torch.empty(L.N, dtype=torch.float64, device=dev) if h is None else h
-    P = Problem(x=prob["x"].data_ptr(), rowop=prob["rowop"].data_ptr(), weight=prob["weight"].data_ptr(),
-                rhs=prob["rhs"].data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(),
-                w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"],
-                activation=prob.get("activation", 0))
+    P = _problem(prob)
     nb = _lib.rfm_assemble_ws_bytes(C.byref(L))
     ws = _ws(nb, dev)
     _check(_lib.rfm_assemble_low(C.byref(L), C.byref(P), int(dtype), _ptr(M), _ptr(h), _ptr(ws), nb, _stream()),
@@ -259,13 +267,21 @@ def evaluation_points(inst, xt: np.ndarray, device="cuda"):
     return tplan, xd
 
 
-def rfm_evaluate(tplan: Plan, xd, prob: dict, a, u_exact=None, ws=None):
-    """u_hat at the test points for coefficients a (device [ncols]); with u_exact (device
-    [T]) also e_L1.  Returns (uhat, e_l1 or None)."""
+def evaluation_ansatz(inst, xt: np.ndarray, device="cuda"):
+    """The instance's hard-constraint factor at the test points (device [T*(1+2d)]), or None."""
+    if inst.ansatz is None:
+        return None
+    return torch.from_numpy(np.ascontiguousarray(inst.ansatz(xt), dtype=np.float64)).to(device)
+
+
+def rfm_evaluate(tplan: Plan, xd, prob: dict, a, u_exact=None, ws=None, ansatz=None):
+    """u_hat at the test points for coefficients a (device [ncols]), times the ansatz factor
+    (evaluation_ansatz) when given; with u_exact (device [T]) also e_L1.  Returns (uhat,
+    e_l1 or None)."""
     L = tplan.layout
     dev = xd.device
     P = Problem(x=xd.data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(), w=prob["w"].data_ptr(),
-                b=prob["b"].data_ptr(), activation=prob.get("activation", 0))
+                b=prob["b"].data_ptr(), activation=prob.get("activation", 0), ansatz=_ptr(ansatz))
     uhat = torch.empty(L.N, dtype=torch.float64, device=dev)
     nb = _lib.rfm_evaluate_ws_bytes(C.byref(L))
     if ws is None or ws.numel() < nb:

@@ -27,7 +27,12 @@ TINY = ["poisson1d", "poisson2d", "heat3d", "helmholtz2d_uneven"]
 # every tiny instance with tanh features, and the sigmoid and sin ablations on each geometry
 ACT_CASES = [(n, "tanh") for n in TINY] + [("poisson1d", "sigmoid"), ("poisson2d", "sin"),
                                            ("heat3d", "sin"), ("helmholtz2d_uneven", "sigmoid"),
-                                           ("poisson2d", "sigmoid"), ("poisson1d", "sin")]
+                                           ("poisson2d", "sigmoid"), ("poisson1d", "sin"),
+                                           # the paper's own problems: coefficient-table rows and
+                                           # the hard-constraint factor
+                                           ("oscillator1d", "tanh"), ("oscillator1d", "sin"),
+                                           ("laplace2d_multiscale", "tanh"),
+                                           ("laplace2d_multiscale", "sigmoid")]
 
 
 @pytest.fixture(scope="module")
@@ -280,10 +285,12 @@ def test_coefficients_match_oracle_back_substitution(rfm):
 
 
 @pytest.mark.parametrize("name,act", [("poisson1d", "tanh"), ("heat3d", "tanh"),
-                                      ("poisson1d", "sigmoid"), ("poisson1d", "sin")])
+                                      ("poisson1d", "sigmoid"), ("poisson1d", "sin"),
+                                      ("oscillator1d", "tanh"), ("laplace2d_multiscale", "tanh")])
 def test_end_to_end_gpu_pipeline(rfm, name, act):
     """Each side with its own factors: report the differences, check the error metric."""
-    inst = I.with_activation(I.tiny(name) if name != "poisson1d" else I.workload("poisson1d"), act)
+    full = name in ("poisson1d", "oscillator1d")
+    inst = I.with_activation(I.workload(name) if full else I.tiny(name), act)
     print(f"[e2e] {name} {act}", flush=True)
     plan, prob = _setup(rfm, inst)
     M, h = rfm.rfm_assemble(plan, prob)
@@ -655,7 +662,8 @@ def test_evaluation_and_l1_error_match_oracle(rfm, name, act):
     prob = rfm.problem_tensors(inst)
     ue = inst.exact(xt)
     tplan, xd = rfm.evaluation_points(inst, xt)
-    uh, e = rfm.rfm_evaluate(tplan, xd, prob, _dev(a), u_exact=_dev(ue))
+    gt = rfm.evaluation_ansatz(inst, xt)
+    uh, e = rfm.rfm_evaluate(tplan, xd, prob, _dev(a), u_exact=_dev(ue), ansatz=gt)
     torch.cuda.synchronize()
     uo = osolve.evaluate(inst, a, xt)
     # absolute-value evaluation of the same formula
@@ -674,12 +682,14 @@ def test_evaluation_and_l1_error_match_oracle(rfm, name, act):
                                       inst.activation)
         W, _, _ = assembly.unnormalised_window(xt[r], inst.mu[j], inst.hw[j])
         scale[r] += (W / S[r]) * (np.abs(phi) @ np.abs(a[k0:k1]))
+    if inst.ansatz is not None:
+        scale *= np.abs(inst.ansatz(xt)[:, 0])
     err = np.abs(uh.cpu().numpy() - uo)
     assert np.all(err <= 64 * U * scale + 1e-300), float((err / (U * scale + 1e-300)).max())
     eo = float(np.mean(np.abs(uo - ue)) / np.std(ue))
     assert abs(e - eo) <= 1e-9 * eo, (e, eo)
     # without the exact solution only u_hat is produced
-    uh2, e2 = rfm.rfm_evaluate(tplan, xd, prob, _dev(a))
+    uh2, e2 = rfm.rfm_evaluate(tplan, xd, prob, _dev(a), ansatz=gt)
     assert e2 is None and torch.equal(uh2, uh)
 
 

@@ -145,13 +145,23 @@ def _fd_operator(inst, a, xr, op):
         return first[:, d - 1] - inst.kappa * lap
     if op == I.OP_HELMHOLTZ:
         return lap + inst.ksq * u0
+    if op >= I.OP_COEF:
+        c = inst.opcoef[op - I.OP_COEF]
+        second = np.zeros((len(xr), d))
+        for i in range(d):
+            xp, xm = xr.copy(), xr.copy()
+            xp[:, i] += e
+            xm[:, i] -= e
+            second[:, i] = (solve.evaluate(inst, a, xp) - 2 * u0 + solve.evaluate(inst, a, xm)) / e**2
+        return c[0] * u0 + first @ c[1:1 + d] + second @ c[1 + d:1 + 2 * d]
     return u0
 
 
 @pytest.mark.parametrize("name,act", [("poisson1d", "tanh"), ("poisson2d", "tanh"), ("heat3d", "tanh"),
                                       ("helmholtz2d_uneven", "tanh"), ("poisson1d", "sigmoid"),
                                       ("poisson2d", "sin"), ("heat3d", "sigmoid"),
-                                      ("helmholtz2d_uneven", "sin")])
+                                      ("helmholtz2d_uneven", "sin"), ("oscillator1d", "tanh"),
+                                      ("laplace2d_multiscale", "tanh"), ("laplace2d_multiscale", "sin")])
 def test_assembled_rows_match_finite_difference_operator(name, act):
     inst = I.with_activation(I.tiny(name), act)
     rows, blocks, h = assembly.assemble(inst)
@@ -172,6 +182,10 @@ def test_assembled_rows_match_finite_difference_operator(name, act):
     vrows = np.nonzero(inst.rowop == I.OP_VALUE)[0]
     val = solve.evaluate(inst, a, inst.x[vrows])
     assert np.allclose(Ma[vrows] / inst.weight[vrows], val, rtol=1e-12, atol=1e-14)
+    # rows of other operators away from the interior pick (the oscillator's u'(0) at t = 0)
+    for r in np.nonzero((inst.rowop >= I.OP_COEF) & (inst.rowop != op))[0]:
+        fdr = _fd_operator(inst, a, inst.x[r:r + 1], inst.rowop[r])
+        assert abs(Ma[r] / inst.weight[r] - fdr[0]) < 2e-4 * max(abs(fdr[0]), scale * 1e-3)
 
 
 def test_row_weights_and_rhs_scaling():
@@ -202,7 +216,8 @@ def test_incidence_strict_support_and_cover_bound():
 @pytest.mark.parametrize("name,act", [("poisson1d", "tanh"), ("heat3d", "tanh"),
                                       ("helmholtz2d_uneven", "tanh"), ("poisson1d", "sigmoid"),
                                       ("heat3d", "sin"), ("helmholtz2d_uneven", "sigmoid"),
-                                      ("poisson2d", "sin")])
+                                      ("poisson2d", "sin"), ("oscillator1d", "tanh"),
+                                      ("laplace2d_multiscale", "tanh")])
 def test_entry_error_scale_bounds_binary64_rounding(name, act):
     """The binary64 assembly sits within a few u * E of an extended-precision evaluation,
     E the absolute-value evaluation used to size the GPU/oracle tolerance."""
