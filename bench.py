@@ -204,6 +204,106 @@ def conditioning_study(args):
     print(json.dumps(out), flush=True)
 
 
+def paper_problems_study(args):
+    """The paper's own problems (the damped oscillator and the multi-scale Laplacian with its
+    hard-constraint trial solution) through the same kernels, with the ablations of its results
+    tables: sigma (tau) in {1e-10, 1e-8, 1e-6, 1e-4, 1e-2} and the sigmoid and sin activations.
+    Per variant: kept columns; kappa(M), kappa(M_hat) and kappa(M_hat S^-1) from the singular
+    values of the dense global matrices (these problems have at most 4,096 columns), scattered
+    on the host from the device's blocks M_j, their kept columns and Q_hat_j; the time of the
+    filter and of 10,000 LSQR iterations with the stop rule off (the paper's protocol); and
+    e_L1 after 500 ... 10,000 iterations (the paper reports the minimum over the run)."""
+    import torch
+
+    from paper_2506_17626_amd import instances as I
+    from paper_2506_17626_amd import rfm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    checkpoints = (500, 1000, 2000, 5000, 10000)
+    variants = [("tanh", 1e-8), ("tanh", 1e-10), ("tanh", 1e-6), ("tanh", 1e-4), ("tanh", 1e-2),
+                ("sigmoid", 1e-8), ("sin", 1e-8)]
+    out = {"study": "paper_problems", "checkpoints": list(checkpoints), "problems": {}}
+
+    def dense_kappa(ho, N, blocks):
+        """kappa of the N-row global matrix with block j = blocks[j] ([|I_j|, c_j]) on the rows
+        I_j and the next c_j columns."""
+        ncol = sum(B.shape[1] for B in blocks)
+        A = np.zeros((N, ncol))
+        c = 0
+        for j, B in enumerate(blocks):
+            A[ho["rows"][ho["row_off"][j]:ho["row_off"][j + 1]], c:c + B.shape[1]] = B
+            c += B.shape[1]
+        sv = np.linalg.svd(A, compute_uv=False)
+        return float(sv[0] / sv[-1]) if sv[-1] > 0 else float("inf")
+
+    def host_blocks(ho, flat, cols):
+        """Block j of a flat column-major device array (leading dimension |I_j|) with cols[j]
+        columns, as [|I_j|, cols[j]] host arrays."""
+        out = []
+        for j, c in enumerate(cols):
+            m = int(ho["row_off"][j + 1] - ho["row_off"][j])
+            o = int(ho["blk_off"][j])
+            out.append(flat[o:o + m * int(c)].reshape(int(c), m).T)
+        return out
+
+    for name in ("oscillator1d", "laplace2d_multiscale"):
+        base = I.workload(name, seed=args.seed)
+        rows = []
+        kM = {}
+        for act, tau in variants:
+            inst = I.with_activation(base, act)
+            plan = rfm.plan_instance(inst)
+            prob = rfm.problem_tensors(inst)
+            M, h = rfm.rfm_assemble(plan, prob)
+            K = np.diff(plan.host["feat_off"])
+            ncols = int(K.sum())
+            fact = rfm.rfm_rrqr_filter(plan, M, tau)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fact = rfm.rfm_rrqr_filter(plan, M, tau, out=fact)
+            torch.cuda.synchronize()
+            filt_ms = 1e3 * (time.perf_counter() - t0)
+            rk = fact["rank"].cpu().numpy()
+            kept = int(rk.sum())
+            xt = inst.test_points()
+            tplan, xd = rfm.evaluation_points(inst, xt)
+            gt = rfm.evaluation_ansatz(inst, xt)
+            ue = torch.from_numpy(inst.exact(xt)).to(dev)
+            errs = {}
+            for it in checkpoints:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                y, info = rfm.rfm_lsqr_solve(plan, fact, h, atol=0.0, btol=0.0, maxit=it, check_every=256,
+                                             use_graph=1)
+                torch.cuda.synchronize()
+                lsqr_s = time.perf_counter() - t0
+                a = rfm.rfm_coefficients(plan, fact, y)
+                _, e = rfm.rfm_evaluate(tplan, xd, prob, a, u_exact=ue, ansatz=gt)
+                errs[str(it)] = e
+            ho = plan.host
+            Mb = host_blocks(ho, M.cpu().numpy(), K)
+            kp = fact["kept"].cpu().numpy()
+            fo = ho["feat_off"]
+            if act not in kM:
+                kM[act] = dense_kappa(ho, inst.N, Mb)
+            k_hat = kM[act] if kept == ncols else dense_kappa(
+                ho, inst.N, [Mb[j][:, kp[fo[j]:fo[j] + rk[j]]] for j in range(plan.J)])
+            k_pre = dense_kappa(ho, inst.N, host_blocks(ho, fact["Q"].cpu().numpy(), rk))
+            row = {"activation": act, "tau": tau, "kept": kept, "columns": ncols,
+                   "drop_pct": 100.0 * (1 - kept / ncols), "kappa_M": kM[act], "kappa_M_hat": k_hat,
+                   "kappa_M_hat_S_inv": k_pre, "filter_ms": filt_ms, "lsqr_10k_s": lsqr_s,
+                   "iters": int(info.iters), "e_l1": errs, "e_l1_min": min(errs.values())}
+            rows.append(row)
+            print(f"[paper problems] {name} {act} sigma={tau:g}: dropped {row['drop_pct']:.0f} %, kappa "
+                  f"M {kM[act]:.1e}, M_hat {k_hat:.1e}, M_hat S^-1 {k_pre:.1e}; filter {filt_ms:.2f} ms, "
+                  f"10k iterations {lsqr_s:.2f} s; e_L1 min {row['e_l1_min']:.2e}", file=sys.stderr, flush=True)
+            del M, fact
+        out["problems"][name] = {"N": base.N, "J": base.J, "columns": int(base.feat_off[-1]), "variants": rows}
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def learned_ceiling(model, ts, Yc):
     """The network's reach (a bound that follows from its shape): every start it can produce lies
     in the affine space {diag(sd) (W3^T z + b3) + mean}, of dimension at most its last hidden width.
@@ -383,6 +483,8 @@ def main():
                     help="filter drop fraction and condition estimates of the preconditioned operator across tau")
     ap.add_argument("--cond-steps", type=int, default=1000)
     ap.add_argument("--cond-workloads", default="poisson1d,poisson2d,heat3d,helmholtz2d_uneven")
+    ap.add_argument("--paper-problems", action="store_true",
+                    help="the oscillator and multi-scale Laplacian with the sigma and activation ablations")
     ap.add_argument("--learned-study", action="store_true",
                     help="run the learned warm-start study on the parametric family instead of the bench")
     ap.add_argument("--n-train", type=int, default=1024)
@@ -396,6 +498,9 @@ def main():
         return
     if args.learned_study:
         learned_study(args)
+        return
+    if args.paper_problems:
+        paper_problems_study(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the kernels are measured on one GPU's share of the "
@@ -427,6 +532,7 @@ def main():
     xt = inst.test_points()
     tplan, xd = rfm.evaluation_points(inst, xt)
     ue = torch.from_numpy(inst.exact(xt)).to(dev)
+    gt = rfm.evaluation_ansatz(inst, xt)
     ews = torch.empty(rfm._lib.rfm_evaluate_ws_bytes(rfm.C.byref(tplan.layout)), dtype=torch.uint8, device=dev)
     e_l1 = []
 
@@ -447,7 +553,7 @@ def main():
         ev[3].record()
         rfm.rfm_coefficients(plan, fact, y, a)
         ev[4].record()
-        _, e = rfm.rfm_evaluate(tplan, xd, prob, a, u_exact=ue, ws=ews)
+        _, e = rfm.rfm_evaluate(tplan, xd, prob, a, u_exact=ue, ws=ews, ansatz=gt)
         ev[5].record()
         e_l1.append(e)
         if record is not None:

@@ -151,10 +151,12 @@ def _paper_geometry(d: int, S: int, delta: float):
     return mu, hw
 
 
-def _full_grid(d: int, n: int) -> np.ndarray:
-    """Regular grid of n points per dim over [0,1]^d, end points included (Section 5,
-    interior collocation points)."""
-    g = np.linspace(0.0, 1.0, n)
+def _full_grid(d: int, n: int, ends: bool) -> np.ndarray:
+    """Regular grid of n points per dim over [0,1]^d (Section 5, interior collocation points):
+    end points included, or cell-centred so that no point lies on the boundary, where a
+    hard-constraint factor vanishes and would leave a zero row (the paper asks for a square
+    or tall M)."""
+    g = np.linspace(0.0, 1.0, n) if ends else (np.arange(n) + 0.5) / n
     return np.stack(np.meshgrid(*([g] * d), indexing="ij"), axis=-1).reshape(-1, d)
 
 
@@ -357,7 +359,7 @@ def oscillator1d(S=20, K=8, omega0=60.0, mu_f=4.0, m=1.0, delta=2.9, seed=0,
         t = x[:, 0]
         return np.exp(-dmp * t) * np.cos(om * t + ph) / math.cos(ph)
 
-    xi = _full_grid(d, S * math.ceil(K))
+    xi = _full_grid(d, S * math.ceil(K), ends=True)
     xb = np.zeros((2, 1))
     NI = xi.shape[0]
     x = np.concatenate([xi, xb])
@@ -405,7 +407,7 @@ def laplace2d_multiscale(S=16, K=16, n=3, delta=2.9, seed=0, name="laplace2d_mul
         F1, F1d, F1dd = _box_factor(a, x[:, 1])
         return np.stack([F0 * F1, F0d * F1, F0 * F1d, F0dd * F1, F0 * F1dd], axis=1)
 
-    xi = _full_grid(d, S * math.ceil(math.sqrt(K)))
+    xi = _full_grid(d, S * math.ceil(math.sqrt(K)), ends=False)
     NI = xi.shape[0]
     rowop = np.full(NI, OP_NEG_LAPLACE, dtype=np.int32)
     weight = np.full(NI, 1 / math.sqrt(NI))
