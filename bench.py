@@ -207,7 +207,8 @@ def conditioning_study(args):
 def paper_problems_study(args):
     """The paper's own problems (the damped oscillator and the multi-scale Laplacian with its
     hard-constraint trial solution) through the same kernels, with the ablations of its results
-    tables: sigma (tau) in {1e-10, 1e-8, 1e-6, 1e-4, 1e-2} and the sigmoid and sin activations.
+    tables: sigma (tau) in {1e-10, 1e-8, 1e-6, 1e-4, 1e-2}, the sigmoid and sin activations,
+    and subdomain networks of depth 3 and 5 (hidden layers as wide as the feature layer).
     Per variant: kept columns; kappa(M), kappa(M_hat) and kappa(M_hat S^-1) from the singular
     values of the dense global matrices (these problems have at most 4,096 columns), scattered
     on the host from the device's blocks M_j, their kept columns and Q_hat_j; the time of the
@@ -221,8 +222,8 @@ def paper_problems_study(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     checkpoints = (500, 1000, 2000, 5000, 10000)
-    variants = [("tanh", 1e-8), ("tanh", 1e-10), ("tanh", 1e-6), ("tanh", 1e-4), ("tanh", 1e-2),
-                ("sigmoid", 1e-8), ("sin", 1e-8)]
+    variants = [("tanh", 1e-8, 1), ("tanh", 1e-10, 1), ("tanh", 1e-6, 1), ("tanh", 1e-4, 1), ("tanh", 1e-2, 1),
+                ("sigmoid", 1e-8, 1), ("sin", 1e-8, 1), ("tanh", 1e-8, 3), ("tanh", 1e-8, 5)]
     out = {"study": "paper_problems", "checkpoints": list(checkpoints), "problems": {}}
 
     def dense_kappa(ho, N, blocks):
@@ -251,8 +252,9 @@ def paper_problems_study(args):
         base = I.workload(name, seed=args.seed)
         rows = []
         kM = {}
-        for act, tau in variants:
-            inst = I.with_activation(base, act)
+        for act, tau, depth in variants:
+            # depth-h networks with hidden layers as wide as the feature layer
+            inst = I.with_depth(I.with_activation(base, act), depth, int(base.meta["K"]), seed=args.seed)
             plan = rfm.plan_instance(inst)
             prob = rfm.problem_tensors(inst)
             M, h = rfm.rfm_assemble(plan, prob)
@@ -285,18 +287,19 @@ def paper_problems_study(args):
             Mb = host_blocks(ho, M.cpu().numpy(), K)
             kp = fact["kept"].cpu().numpy()
             fo = ho["feat_off"]
-            if act not in kM:
-                kM[act] = dense_kappa(ho, inst.N, Mb)
-            k_hat = kM[act] if kept == ncols else dense_kappa(
+            key = (act, depth)
+            if key not in kM:
+                kM[key] = dense_kappa(ho, inst.N, Mb)
+            k_hat = kM[key] if kept == ncols else dense_kappa(
                 ho, inst.N, [Mb[j][:, kp[fo[j]:fo[j] + rk[j]]] for j in range(plan.J)])
             k_pre = dense_kappa(ho, inst.N, host_blocks(ho, fact["Q"].cpu().numpy(), rk))
-            row = {"activation": act, "tau": tau, "kept": kept, "columns": ncols,
-                   "drop_pct": 100.0 * (1 - kept / ncols), "kappa_M": kM[act], "kappa_M_hat": k_hat,
+            row = {"activation": act, "tau": tau, "depth": depth, "kept": kept, "columns": ncols,
+                   "drop_pct": 100.0 * (1 - kept / ncols), "kappa_M": kM[key], "kappa_M_hat": k_hat,
                    "kappa_M_hat_S_inv": k_pre, "filter_ms": filt_ms, "lsqr_10k_s": lsqr_s,
                    "iters": int(info.iters), "e_l1": errs, "e_l1_min": min(errs.values())}
             rows.append(row)
-            print(f"[paper problems] {name} {act} sigma={tau:g}: dropped {row['drop_pct']:.0f} %, kappa "
-                  f"M {kM[act]:.1e}, M_hat {k_hat:.1e}, M_hat S^-1 {k_pre:.1e}; filter {filt_ms:.2f} ms, "
+            print(f"[paper problems] {name} {act} h={depth} sigma={tau:g}: dropped {row['drop_pct']:.0f} %, kappa "
+                  f"M {kM[key]:.1e}, M_hat {k_hat:.1e}, M_hat S^-1 {k_pre:.1e}; filter {filt_ms:.2f} ms, "
                   f"10k iterations {lsqr_s:.2f} s; e_L1 min {row['e_l1_min']:.2e}", file=sys.stderr, flush=True)
             del M, fact
         out["problems"][name] = {"N": base.N, "J": base.J, "columns": int(base.feat_off[-1]), "variants": rows}

@@ -106,6 +106,8 @@ typedef enum {
 /* Discretised problem (Section 2.1 and Section 4.2): subdomain geometry, random
  * features phi_jk = act(w_jk . (x - mu_j)/hw_j + b_jk) (eq. fcn_depth_h, depth 1,
  * inputs normalised to [-1,1] per subdomain), points and per-row data.
+ * With depth h > 1 each subdomain's features share h-1 hidden layers
+ *   z0 = (x - mu_j)/hw_j,  z_l = act(W_l z_{l-1} + b_l),  phi_jk = act(w_jk . z_{h-1} + b_jk).
  * A hard-constraint ansatz (Section 5.1: u~ = g u_hat, after Lagaris et al.) is given by its
  * factor g per point: ansatz [N*(1+2d)] holds, for point r, g, d_i g (i < d) and d_ii g
  * (i < d) at offset r*(1+2d); the row operators then apply to g u_hat (product rule), and
@@ -126,6 +128,14 @@ typedef struct {
   const double *opcoef;   /* device [nopcoef*(1+2d)]: per operator c0, c1_0..c1_{d-1},
                              c2_0..c2_{d-1}; nullable when nopcoef = 0      */
   const double *ansatz;   /* device [N*(1+2d)] g, d_i g, d_ii g per point, or NULL (g = 1) */
+  int32_t depth;          /* h of eq. fcn_depth_h: 0 or 1 = features on the input, 2..8 =
+                             h-1 hidden layers of width `hidden` shared by a subdomain's
+                             features, which then act on the last hidden layer            */
+  int32_t hidden;         /* width H of the hidden layers (1..16) when depth > 1           */
+  const double *net;      /* device, when depth > 1: per subdomain j, at offset
+                             j*(H*d + H + (depth-2)*(H*H + H)), layer 1 W [H x d] row-major
+                             then b [H], then layers 2..depth-1 W [H x H] row-major then b [H];
+                             w is then [ncols*H] (feature weights on the last hidden layer) */
 } rfm_problem;
 
 /* Planning (sync, host only).  Builds the supports I_j of eq. DomainDecomp from host

@@ -153,6 +153,52 @@ def _coef_rows(op: np.ndarray, opcoef, d: int):
     return c0, c1, c2, use
 
 
+def network_layers(inst, j):
+    """Hidden layers (W [H, fan_in], b [H]) of subdomain j's depth-h network, read from the
+    instance's flat per-subdomain parameters (layer 1 on the d inputs, then H x H layers)."""
+    H, d = inst.hidden, inst.d
+    row = inst.net[j]
+    layers = [(row[:H * d].reshape(H, d), row[H * d:H * d + H])]
+    o = H * d + H
+    for _ in range(inst.depth - 2):
+        layers.append((row[o:o + H * H].reshape(H, H), row[o + H * H:o + H * H + H]))
+        o += H * H + H
+    return layers
+
+
+def network_features(x, mu_j, hw_j, layers, wk, bk, act: str = "tanh"):
+    """Features of a depth-h network (eq. fcn_depth_h): z_0 = xn, z_l = Xi(W_l z_(l-1) + b_l),
+    phi_k = Xi(w_k . z_(h-1) + b_k).  Derivatives in x by the chain rule carried forward per
+    layer: d_a z_l = Xi'(s) d_a s, d_aa z_l = Xi''(s) (d_a s)^2 + Xi'(s) d_aa s with
+    d_a s = W_l d_a z_(l-1).  Returns phi [m, K], d_a phi [m, K, d], d_aa phi [m, K, d]."""
+    m, d = x.shape
+    z = (x - mu_j[None, :]) / hw_j[None, :]
+    dz = np.zeros((m, d, d))
+    for a in range(d):
+        dz[:, a, a] = 1.0 / hw_j[a]
+    ddz = np.zeros((m, d, d))
+    for W, b in layers:
+        s = z @ W.T + b[None, :]
+        ds, dds = dz @ W.T, ddz @ W.T
+        t, g, gg = activation(act, s)
+        z, dz, ddz = t, g[:, None, :] * ds, gg[:, None, :] * ds * ds + g[:, None, :] * dds
+    s = z @ wk.T + bk[None, :]
+    ds, dds = dz @ wk.T, ddz @ wk.T
+    t, g, gg = activation(act, s)
+    dphi = g[:, None, :] * ds
+    ddphi = gg[:, None, :] * ds * ds + g[:, None, :] * dds
+    return t, dphi.transpose(0, 2, 1), ddphi.transpose(0, 2, 1)
+
+
+def block_features(inst, j, x):
+    """phi, d_a phi, d_aa phi of subdomain j's features at points x (depth 1 or deeper)."""
+    k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
+    if inst.depth <= 1:
+        return features(x, inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1], inst.activation)
+    return network_features(x, inst.mu[j], inst.hw[j], network_layers(inst, j), inst.w[k0:k1],
+                            inst.b[k0:k1], inst.activation)
+
+
 def apply_rowop(op: np.ndarray, psi, dpsi, ddpsi, kappa: float, ksq: float, opcoef=None):
     """Row operator applied to psi = w phi given its derivatives ([m,K], [m,K,d], [m,K,d])."""
     d = dpsi.shape[2]
@@ -198,8 +244,7 @@ def assemble(inst):
         k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
         x = inst.x[r]
         w, dw, ddw = wins[j]
-        phi, dphi, ddphi = features(x, inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1],
-                                    inst.activation)
+        phi, dphi, ddphi = block_features(inst, j, x)
         psi = w[:, None] * phi
         dpsi = dw[:, None, :] * phi[:, :, None] + w[:, None, None] * dphi
         ddpsi = (ddw[:, None, :] * phi[:, :, None] + 2.0 * dw[:, None, :] * dphi
@@ -265,11 +310,14 @@ def entry_error_scale(inst, rows, j):
     k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
     wk, bk = inst.w[k0:k1], inst.b[k0:k1]
     xn = (inst.x[r] - inst.mu[j][None, :]) / inst.hw[j][None, :]
-    sarg = np.abs(xn) @ np.abs(wk).T + np.abs(bk)[None, :]
-    ta, ga, gga = _activation_bounds(inst.activation, xn @ wk.T + bk[None, :], sarg)
-    sc = np.abs(wk / inst.hw[j][None, :])
-    dphia = ga[:, :, None] * sc[None, :, :]
-    ddphia = gga[:, :, None] * (sc * sc)[None, :, :]
+    if inst.depth <= 1:
+        sarg = np.abs(xn) @ np.abs(wk).T + np.abs(bk)[None, :]
+        ta, ga, gga = _activation_bounds(inst.activation, xn @ wk.T + bk[None, :], sarg)
+        sc = np.abs(wk / inst.hw[j][None, :])
+        dphia = ga[:, :, None] * sc[None, :, :]
+        ddphia = gga[:, :, None] * (sc * sc)[None, :, :]
+    else:
+        ta, dphia, ddphia = _network_bounds(inst, j, xn, wk, bk)
     psia = wa[:, None] * ta
     dpsia = dwa[:, None, :] * ta[:, :, None] + wa[:, None, None] * dphia
     ddpsia = ddwa[:, None, :] * ta[:, :, None] + 2.0 * dwa[:, None, :] * dphia + wa[:, None, None] * ddphia
@@ -310,6 +358,62 @@ def _activation_bounds(name: str, s: np.ndarray, sarg: np.ndarray):
         sn, cs = np.abs(np.sin(s)), np.abs(np.cos(s))
         return sn + cs * sarg, cs + sn * sarg, sn + cs * sarg
     raise ValueError(f"unknown activation {name!r}")
+
+
+def _activation_terms(name: str, s: np.ndarray):
+    """|Xi|, |Xi'|, |Xi''| and |Xi'''| at s, and the absolute-value evaluations of the
+    formulas for Xi' and Xi'' in terms of t = Xi(s) (their own rounding allowance)."""
+    if name == "tanh":
+        t = np.tanh(s)
+        g = 1.0 - t * t
+        return (np.abs(t), g, 2.0 * np.abs(t) * g, 2.0 * g * np.abs(1.0 - 3.0 * t * t), 1.0 + t * t,
+                2.0 * np.abs(t) * (1.0 + t * t))
+    if name == "sigmoid":
+        with np.errstate(over="ignore"):
+            t = 1.0 / (1.0 + np.exp(-s))
+        g = t * (1.0 - t)
+        ag = t * (1.0 + t)
+        return t, g, np.abs(g * (1.0 - 2.0 * t)), np.abs(g * (1.0 - 6.0 * g)), ag, ag * (1.0 + 2.0 * t)
+    if name == "sin":
+        sn, cs = np.abs(np.sin(s)), np.abs(np.cos(s))
+        return sn, cs, sn, cs, cs, sn
+    raise ValueError(f"unknown activation {name!r}")
+
+
+def _network_bounds(inst, j, xn, wk, bk):
+    """Running error bounds (in units of u) of phi, d_a phi, d_aa phi for a depth-h network,
+    carried through the layers as a pair (magnitude M, error E) for every quantity:
+    E(a b) = E_a M_b + M_a E_b + M_a M_b and E(sum) = sum of E + M(sum) for products and sums,
+    E(Xi(s)) = |Xi'(s)| E_s + |Xi(s)| for an activation (its own rounding relative to its
+    value); M is the absolute-value evaluation."""
+    m, d = xn.shape
+    Mz, Ez = np.abs(xn), np.abs(xn)
+    Mdz = np.zeros((m, d, d))
+    for a in range(d):
+        Mdz[:, a, a] = 1.0 / inst.hw[j][a]
+    Edz = Mdz.copy()
+    Mddz, Eddz = np.zeros_like(Mdz), np.zeros_like(Mdz)
+    z = xn
+    for W, b in network_layers(inst, j) + [(wk, bk)]:
+        aW = np.abs(W).T
+        s = z @ W.T + b[None, :]
+        Ms = Mz @ aW + np.abs(b)[None, :]
+        Es = Ez @ aW + Ms
+        Mds, Eds = Mdz @ aW, Edz @ aW + Mdz @ aW
+        Mdds, Edds = Mddz @ aW, Eddz @ aW + Mddz @ aW
+        t, g, gg, g3, Ag, Agg = _activation_terms(inst.activation, s)
+        Eg = (gg * Es + Ag)[:, None, :]           # error of Xi'(s)
+        Egg = (g3 * Es + Agg)[:, None, :]         # error of Xi''(s)
+        g_, gg_ = g[:, None, :], gg[:, None, :]
+        Mdz_n = g_ * Mds
+        Edz_n = Eg * Mds + g_ * Eds + Mdz_n
+        Mddz_n = gg_ * Mds * Mds + g_ * Mdds
+        Eddz_n = (Egg * Mds * Mds + gg_ * (2.0 * Mds * Eds + Mds * Mds) + Eg * Mdds + g_ * Edds
+                  + g_ * Mdds + Mddz_n)
+        Mz, Ez = t, g * Es + t
+        Mdz, Edz, Mddz, Eddz = Mdz_n, Edz_n, Mddz_n, Eddz_n
+        z = activation(inst.activation, s)[0]
+    return Ez, Edz.transpose(0, 2, 1), Eddz.transpose(0, 2, 1)
 
 
 def global_dense(inst, rows, blocks):

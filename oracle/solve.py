@@ -58,8 +58,7 @@ def evaluate(inst, a: np.ndarray, xt: np.ndarray) -> np.ndarray:
         if r.size == 0:
             continue
         k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
-        phi, _, _ = assembly.features(xt[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1],
-                                      inst.activation)
+        phi, _, _ = assembly.block_features(inst, j, xt[r])
         u[r] += (what[j] / S[r]) * (phi @ a[k0:k1])
     if inst.ansatz is not None:
         u = u * np.asarray(inst.ansatz(xt))[:, 0]   # u~ = g u_hat

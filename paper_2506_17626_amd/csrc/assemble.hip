@@ -11,7 +11,8 @@
 //   with coalesced 64-wide stores; each thread produces a run of features for its row,
 //   reusing the row's point and window data.  Entry = s_r Op_r[w_j phi_jk](x_r) by the
 //   product rule with phi = Xi(w . xn + b), xn = (x - mu_j)/hw_j (eq. fcn_depth_h), Xi the
-//   problem's activation (tanh, sigmoid or sin).
+//   problem's activation (tanh, sigmoid or sin); with a depth-h network the features act on the
+//   last hidden layer, evaluated per row with forward-mode derivatives (hidden_forward).
 // Both run in binary64, or in binary32 for the precision form (rfm_assemble_low), whose
 // entries are stored as binary32 or bfloat16.
 #include "common.hpp"
@@ -134,7 +135,84 @@ template <> struct Out<uint16_t> {
   }
 };
 
-template <int D, typename Tc, typename To>
+// Hidden layers of a depth-h subdomain network (eq. fcn_depth_h) with forward-mode first and
+// pure second derivatives in x: z, d_a z, d_aa z of the last hidden layer, width H <= kHMax
+// (entries u >= H stay 0).  z0 = xn has d_a z0 = e_a / hw_a and no second derivative.
+template <int D, typename Tc>
+__device__ __forceinline__ void hidden_forward(const rfm_problem &P, int j, const Tc *xn, const Tc *hwj,
+                                               Tc (&z)[kHMax], Tc (&dz)[D][kHMax], Tc (&ddz)[D][kHMax]) {
+  const int H = P.hidden;
+  const double *net = P.net + (int64_t)j * net_stride(P, D);
+  // layer 1 on the normalised input
+#pragma unroll
+  for (int u = 0; u < kHMax; ++u) {
+    z[u] = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) dz[a][u] = ddz[a][u] = 0;
+    if (u < H) {
+      Tc s = (Tc)net[H * D + u];
+#pragma unroll
+      for (int a = 0; a < D; ++a) s += (Tc)net[u * D + a] * xn[a];
+      Tc t, g, gg;
+      activation3<Tc>(P.activation, s, t, g, gg);
+      z[u] = t;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const Tc sc = (Tc)net[u * D + a] / hwj[a];
+        dz[a][u] = g * sc;
+        ddz[a][u] = gg * (sc * sc);
+      }
+    }
+  }
+  net += H * D + H;
+  // layers 2 .. h-1
+  for (int l = 2; l < P.depth; ++l, net += H * H + H) {
+    Tc nz[kHMax], ndz[D][kHMax], nddz[D][kHMax];
+#pragma unroll
+    for (int u = 0; u < kHMax; ++u) {
+      nz[u] = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) ndz[a][u] = nddz[a][u] = 0;
+      if (u < H) {
+        Tc s = (Tc)net[H * H + u], ds[D], dds[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) ds[a] = dds[a] = 0;
+#pragma unroll
+        for (int v = 0; v < kHMax; ++v) {
+          if (v < H) {
+            const Tc wv = (Tc)net[u * H + v];
+            s += wv * z[v];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              ds[a] += wv * dz[a][v];
+              dds[a] += wv * ddz[a][v];
+            }
+          }
+        }
+        Tc t, g, gg;
+        activation3<Tc>(P.activation, s, t, g, gg);
+        nz[u] = t;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          ndz[a][u] = g * ds[a];
+          nddz[a][u] = gg * ds[a] * ds[a] + g * dds[a];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kHMax; ++u) {
+      z[u] = nz[u];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        dz[a][u] = ndz[a][u];
+        ddz[a][u] = nddz[a][u];
+      }
+    }
+  }
+}
+
+// DEEP: features on the last hidden layer of a depth-h network (P.depth > 1).
+template <int D, typename Tc, typename To, bool DEEP>
 __global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, rfm_problem P,
                                                                   const Tc *win, To *M) {
   const int j = blockIdx.z;
@@ -183,25 +261,59 @@ __global__ __launch_bounds__(kRowsPerBlock) void assemble_entries(rfm_layout L, 
       op = RFM_OP_VALUE;
     }
   }
+  constexpr int HM = DEEP ? kHMax : 1;
+  Tc z[HM], dz[D][HM], ddz[D][HM];
+  if constexpr (DEEP) hidden_forward<D, Tc>(P, j, xn, hwj, z, dz, ddz);
   To *out = M + L.blk_off[j] + (int64_t)i;
   const int k1 = min(K, k0 + kFeatPerThread);
   for (int k = k0; k < k1; ++k) {
-    const double *wk = P.w + (f0 + k) * D;
-    Tc s = 0;
+    Tc t, dphi[D], ddphi[D];  // phi and its derivatives in x
+    if constexpr (DEEP) {
+      const int H = P.hidden;
+      const double *wk = P.w + (f0 + k) * H;
+      Tc s = (Tc)P.b[f0 + k], ds[D], dds[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) s += xn[a] * (Tc)wk[a];
-    s += (Tc)P.b[f0 + k];
-    Tc t, g, gg;  // phi, phi', phi'' of the activation at s
-    activation3<Tc>(P.activation, s, t, g, gg);
+      for (int a = 0; a < D; ++a) ds[a] = dds[a] = 0;
+#pragma unroll
+      for (int u = 0; u < kHMax; ++u) {
+        if (u < H) {
+          const Tc wu = (Tc)wk[u];
+          s += wu * z[u];
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            ds[a] += wu * dz[a][u];
+            dds[a] += wu * ddz[a][u];
+          }
+        }
+      }
+      Tc g, gg;
+      activation3<Tc>(P.activation, s, t, g, gg);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        dphi[a] = g * ds[a];
+        ddphi[a] = gg * ds[a] * ds[a] + g * dds[a];
+      }
+    } else {
+      const double *wk = P.w + (f0 + k) * D;
+      Tc s = 0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) s += xn[a] * (Tc)wk[a];
+      s += (Tc)P.b[f0 + k];
+      Tc g, gg;  // phi, phi', phi'' of the activation at s
+      activation3<Tc>(P.activation, s, t, g, gg);
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const Tc sc = (Tc)wk[a] / hwj[a];
+        dphi[a] = g * sc;
+        ddphi[a] = gg * (sc * sc);
+      }
+    }
     const Tc psi = w * t;
     Tc lap = 0, spatial = 0, dlast = 0, gen = c0 * psi;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const Tc sc = (Tc)wk[a] / hwj[a];
-      const Tc dphi = g * sc;
-      const Tc ddphi = gg * (sc * sc);
-      const Tc dpsi = dw[a] * t + w * dphi;
-      const Tc ddpsi = ddw[a] * t + (Tc)2 * dw[a] * dphi + w * ddphi;
+      const Tc dpsi = dw[a] * t + w * dphi[a];
+      const Tc ddpsi = ddw[a] * t + (Tc)2 * dw[a] * dphi[a] + w * ddphi[a];
       lap += ddpsi;
       if (a < D - 1) spatial += ddpsi;
       if (a == D - 1) dlast = dpsi;
@@ -224,7 +336,10 @@ rfm_status launch(const rfm_layout *L, const rfm_problem *P, To *M, double *h, T
   RFM_LAUNCH_CHECK();
   if (L->max_rows > 0 && L->max_cols > 0) {
     dim3 grid(ceil_div(L->max_rows, kRowsPerBlock), ceil_div(L->max_cols, kFeatPerThread), L->J);
-    hipLaunchKernelGGL((assemble_entries<D, Tc, To>), grid, dim3(kRowsPerBlock), 0, st, *L, *P, win, M);
+    if (P->depth > 1)
+      hipLaunchKernelGGL((assemble_entries<D, Tc, To, true>), grid, dim3(kRowsPerBlock), 0, st, *L, *P, win, M);
+    else
+      hipLaunchKernelGGL((assemble_entries<D, Tc, To, false>), grid, dim3(kRowsPerBlock), 0, st, *L, *P, win, M);
     RFM_LAUNCH_CHECK();
   }
   return RFM_OK;
@@ -250,6 +365,8 @@ rfm_status check_problem(const rfm_layout *L, const rfm_problem *P, const void *
     return fail(RFM_EINVAL, std::string(who) + ": operator table size or pointer");
   if (P->activation < RFM_ACT_TANH || P->activation > RFM_ACT_SIN)
     return fail(RFM_EINVAL, std::string(who) + ": unknown activation");
+  s = check_network(P, who);
+  if (s != RFM_OK) return s;
   if (!h || (L->nnz > 0 && !M)) return fail(RFM_EINVAL, std::string(who) + ": null output");
   if (ws_bytes < rfm_assemble_ws_bytes(L) || (rfm_assemble_ws_bytes(L) > 0 && !ws))
     return fail(RFM_EINVAL, std::string(who) + ": workspace too small");

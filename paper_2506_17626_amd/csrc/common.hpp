@@ -122,6 +122,23 @@ __device__ __forceinline__ T activation1(int act, T s) {
   return tanh(s);
 }
 
+// Widest hidden layer of a depth-h feature network (held in registers per row).
+constexpr int kHMax = 16;
+constexpr int kMaxDepth = 8;
+
+// Doubles per subdomain in rfm_problem::net.
+__host__ __device__ inline int64_t net_stride(const rfm_problem &P, int d) {
+  const int64_t H = P.hidden;
+  return H * d + H + (int64_t)(P.depth - 2) * (H * H + H);
+}
+
+inline rfm_status check_network(const rfm_problem *P, const char *who) {
+  if (P->depth < 0 || P->depth > kMaxDepth) return fail(RFM_EINVAL, std::string(who) + ": depth out of range");
+  if (P->depth > 1 && (P->hidden < 1 || P->hidden > kHMax || !P->net))
+    return fail(RFM_EINVAL, std::string(who) + ": hidden width (1..16) or network pointer");
+  return RFM_OK;
+}
+
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace rfm

@@ -1,7 +1,8 @@
 // Evaluation of the solution at test points and its L1 error (Sec. 4.2 performance
 // evaluation): u_hat(x) = sum over the subdomains j covering x of w_j(x) phi_j(x)^T a_j
 // (eq. elm_solution with the partition-of-unity windows of eq. used_window_function_nd),
-// times a hard-constraint ansatz factor g(x) when the problem has one (Section 5.1), and
+// times a hard-constraint ansatz factor g(x) when the problem has one (Section 5.1), with the
+// features of a depth-h network acting on its last hidden layer when depth > 1, and
 // e_L1 = mean |u_hat - u| / std(u).
 //
 // eval_points: one thread per test point; the covering subdomains in ascending j (the
@@ -31,7 +32,41 @@ __device__ __forceinline__ double window_hat(const double *xr, const double *mu,
   return W;
 }
 
+// Last hidden layer of a depth-h subdomain network at xn (values only; entries u >= H are 0).
 template <int D>
+__device__ __forceinline__ void hidden_value(const rfm_problem &P, int j, const double *xn, double (&z)[kHMax]) {
+  const int H = P.hidden;
+  const double *net = P.net + (int64_t)j * net_stride(P, D);
+#pragma unroll
+  for (int u = 0; u < kHMax; ++u) {
+    z[u] = 0.0;
+    if (u < H) {
+      double s = net[H * D + u];
+#pragma unroll
+      for (int a = 0; a < D; ++a) s += net[u * D + a] * xn[a];
+      z[u] = activation1<double>(P.activation, s);
+    }
+  }
+  net += H * D + H;
+  for (int l = 2; l < P.depth; ++l, net += H * H + H) {
+    double nz[kHMax];
+#pragma unroll
+    for (int u = 0; u < kHMax; ++u) {
+      nz[u] = 0.0;
+      if (u < H) {
+        double s = net[H * H + u];
+#pragma unroll
+        for (int v = 0; v < kHMax; ++v)
+          if (v < H) s += net[u * H + v] * z[v];
+        nz[u] = activation1<double>(P.activation, s);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kHMax; ++u) z[u] = nz[u];
+  }
+}
+
+template <int D, bool DEEP>
 __global__ __launch_bounds__(kEvalThreads) void eval_points(rfm_layout L, rfm_problem P, const double *__restrict__ a,
                                                             double *__restrict__ uhat,
                                                             const double *__restrict__ ue, double *part) {
@@ -58,11 +93,24 @@ __global__ __launch_bounds__(kEvalThreads) void eval_points(rfm_layout L, rfm_pr
       for (int i = 0; i < D; ++i) xn[i] = (xr[i] - mu[i]) / hw[i];
       const int64_t f0 = L.feat_off[j], f1 = L.feat_off[j + 1];
       double acc = 0.0;
-      for (int64_t k = f0; k < f1; ++k) {
-        double s = P.b[k];
+      if constexpr (DEEP) {
+        double z[kHMax];
+        hidden_value<D>(P, j, xn, z);
+        const int H = P.hidden;
+        for (int64_t k = f0; k < f1; ++k) {
+          double s = P.b[k];
 #pragma unroll
-        for (int i = 0; i < D; ++i) s += xn[i] * P.w[k * D + i];
-        acc += a[k] * activation1<double>(P.activation, s);
+          for (int u = 0; u < kHMax; ++u)
+            if (u < H) s += P.w[k * H + u] * z[u];
+          acc += a[k] * activation1<double>(P.activation, s);
+        }
+      } else {
+        for (int64_t k = f0; k < f1; ++k) {
+          double s = P.b[k];
+#pragma unroll
+          for (int i = 0; i < D; ++i) s += xn[i] * P.w[k * D + i];
+          acc += a[k] * activation1<double>(P.activation, s);
+        }
       }
       u += w * acc;
     }
@@ -108,7 +156,10 @@ template <int D>
 rfm_status launch_eval(const rfm_layout *L, const rfm_problem *P, const double *a, double *uhat, const double *ue,
                        double *part, double *sums, hipStream_t st) {
   const unsigned g = ceil_div(L->N, kEvalThreads);
-  hipLaunchKernelGGL(eval_points<D>, dim3(g), dim3(kEvalThreads), 0, st, *L, *P, a, uhat, ue, part);
+  if (P->depth > 1)
+    hipLaunchKernelGGL((eval_points<D, true>), dim3(g), dim3(kEvalThreads), 0, st, *L, *P, a, uhat, ue, part);
+  else
+    hipLaunchKernelGGL((eval_points<D, false>), dim3(g), dim3(kEvalThreads), 0, st, *L, *P, a, uhat, ue, part);
   RFM_LAUNCH_CHECK();
   if (ue) {
     hipLaunchKernelGGL(eval_reduce, dim3(1), dim3(1024), 0, st, part, (int64_t)g, 2, sums);
@@ -137,6 +188,8 @@ extern "C" rfm_status rfm_evaluate(const rfm_layout *L, const rfm_problem *P, co
   if ((u_exact || e_l1) && (!u_exact || !e_l1)) return fail(RFM_EINVAL, "rfm_evaluate: u_exact and e_l1 go together");
   if (P->activation < RFM_ACT_TANH || P->activation > RFM_ACT_SIN)
     return fail(RFM_EINVAL, "rfm_evaluate: unknown activation");
+  s = check_network(P, "rfm_evaluate");
+  if (s != RFM_OK) return s;
   if (!ws || ws_bytes < rfm_evaluate_ws_bytes(L)) return fail(RFM_EINVAL, "rfm_evaluate: workspace too small");
   hipStream_t st = (hipStream_t)stream;
   double *sums = (double *)ws, *part = sums + 4;

@@ -97,6 +97,9 @@ class Instance:
     activation: str = "tanh"  # feature activation: "tanh", "sigmoid" or "sin"
     opcoef: np.ndarray | None = None  # [nop, 1+2d] c0, c1_i, c2_i of the OP_COEF + i rows
     ansatz: object = None   # callable x[n,d] -> [n, 1+2d]: g, d_i g, d_ii g of u~ = g u_hat
+    depth: int = 1          # h of the subdomain networks; > 1: hidden layers of width `hidden`
+    hidden: int = 0
+    net: np.ndarray | None = None  # [J, H d + H + (h-2)(H H + H)] hidden parameters per subdomain
 
     @property
     def N(self) -> int:
@@ -441,6 +444,29 @@ def with_activation(inst: Instance, activation: str) -> Instance:
     if activation not in ("tanh", "sigmoid", "sin"):
         raise ValueError(f"unknown activation {activation!r}")
     return replace(inst, activation=activation, name=f"{inst.name}_{activation}")
+
+
+def with_depth(inst: Instance, depth: int, hidden: int, seed: int = 0) -> Instance:
+    """The same instance with depth-h subdomain networks (eq. fcn_depth_h; Section 5's
+    ablations use h = 3 and 5): h-1 hidden layers of width `hidden` per subdomain, and the
+    features acting on the last of them.  Weights uniform LeCun (U(-sqrt(3/fan_in),
+    sqrt(3/fan_in)), Section 5, network architecture), biases U(-1,1) as for depth 1."""
+    if depth <= 1:
+        return inst
+    rng = Rng(seed, 11)
+    H, d = hidden, inst.d
+    lim = lambda fan_in: math.sqrt(3.0 / fan_in)
+    rows = []
+    for _ in range(inst.J):
+        parts = [rng.uniform(-lim(d), lim(d), H * d), rng.uniform(-1.0, 1.0, H)]
+        for _ in range(depth - 2):
+            parts += [rng.uniform(-lim(H), lim(H), H * H), rng.uniform(-1.0, 1.0, H)]
+        rows.append(np.concatenate(parts))
+    n = int(inst.feat_off[-1])
+    w = rng.uniform(-lim(H), lim(H), n * H).reshape(n, H)
+    b = rng.uniform(-1.0, 1.0, n)
+    return replace(inst, depth=depth, hidden=H, net=np.stack(rows), w=w, b=b,
+                   name=f"{inst.name}_h{depth}")
 
 
 def tiny(name: str, seed: int = 0) -> Instance:

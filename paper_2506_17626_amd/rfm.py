@@ -41,7 +41,8 @@ class Layout(C.Structure):
 class Problem(C.Structure):
     _fields_ = [("x", _p), ("rowop", _p), ("weight", _p), ("rhs", _p), ("mu", _p), ("hw", _p),
                 ("w", _p), ("b", _p), ("kappa", C.c_double), ("ksq", C.c_double), ("activation", C.c_int32),
-                ("nopcoef", C.c_int32), ("opcoef", _p), ("ansatz", _p)]
+                ("nopcoef", C.c_int32), ("opcoef", _p), ("ansatz", _p),
+                ("depth", C.c_int32), ("hidden", C.c_int32), ("net", _p)]
 
 ACTIVATIONS = {"tanh": 0, "sigmoid": 1, "sin": 2}
 
@@ -200,7 +201,9 @@ def problem_tensors(inst, device="cuda") -> dict:
                 kappa=float(inst.kappa), ksq=float(inst.ksq),
                 activation=ACTIVATIONS[inst.activation],
                 opcoef=None if inst.opcoef is None else t(inst.opcoef, torch.float64),
-                ansatz=None if inst.ansatz is None else t(inst.ansatz(inst.x), torch.float64))
+                ansatz=None if inst.ansatz is None else t(inst.ansatz(inst.x), torch.float64),
+                depth=int(inst.depth), hidden=int(inst.hidden),
+                net=None if inst.net is None else t(inst.net, torch.float64))
 
 
 def _problem(prob: dict) -> Problem:
@@ -211,7 +214,8 @@ def _problem(prob: dict) -> Problem:
                    rhs=prob["rhs"].data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(),
                    w=prob["w"].data_ptr(), b=prob["b"].data_ptr(), kappa=prob["kappa"], ksq=prob["ksq"],
                    activation=prob.get("activation", 0), nopcoef=0 if oc is None else oc.shape[0],
-                   opcoef=_ptr(oc), ansatz=_ptr(an))
+                   opcoef=_ptr(oc), ansatz=_ptr(an), depth=prob.get("depth", 1), hidden=prob.get("hidden", 0),
+                   net=_ptr(prob.get("net")))
 
 
 def plan_instance(inst, device="cuda") -> Plan:
@@ -281,7 +285,8 @@ def rfm_evaluate(tplan: Plan, xd, prob: dict, a, u_exact=None, ws=None, ansatz=N
     L = tplan.layout
     dev = xd.device
     P = Problem(x=xd.data_ptr(), mu=prob["mu"].data_ptr(), hw=prob["hw"].data_ptr(), w=prob["w"].data_ptr(),
-                b=prob["b"].data_ptr(), activation=prob.get("activation", 0), ansatz=_ptr(ansatz))
+                b=prob["b"].data_ptr(), activation=prob.get("activation", 0), ansatz=_ptr(ansatz),
+                depth=prob.get("depth", 1), hidden=prob.get("hidden", 0), net=_ptr(prob.get("net")))
     uhat = torch.empty(L.N, dtype=torch.float64, device=dev)
     nb = _lib.rfm_evaluate_ws_bytes(C.byref(L))
     if ws is None or ws.numel() < nb:

@@ -33,6 +33,21 @@ ACT_CASES = [(n, "tanh") for n in TINY] + [("poisson1d", "sigmoid"), ("poisson2d
                                            ("oscillator1d", "tanh"), ("oscillator1d", "sin"),
                                            ("laplace2d_multiscale", "tanh"),
                                            ("laplace2d_multiscale", "sigmoid")]
+# depth-h subdomain networks (hidden width H): (name, activation, h, H)
+DEEP_CASES = [("poisson1d", "tanh", 3, 8), ("poisson2d", "tanh", 3, 16), ("heat3d", "sin", 3, 8),
+              ("helmholtz2d_uneven", "sigmoid", 3, 16), ("oscillator1d", "tanh", 5, 8),
+              ("laplace2d_multiscale", "tanh", 5, 16)]
+CASES = [(n, a, 1, 0) for n, a in ACT_CASES] + DEEP_CASES
+
+
+def _case_id(c):
+    return f"{c[0]}-{c[1]}" + (f"-h{c[2]}x{c[3]}" if c[2] > 1 else "")
+
+
+def _instance(case, full=False):
+    name, act, depth, hidden = case
+    inst = I.with_activation(I.workload(name) if full else I.tiny(name), act)
+    return I.with_depth(inst, depth, hidden)
 
 
 @pytest.fixture(scope="module")
@@ -53,9 +68,10 @@ def _setup(rfm, inst):
     return plan, prob
 
 
-@pytest.mark.parametrize("name,act", ACT_CASES)
-def test_assembly_matches_oracle(rfm, name, act):
-    inst = I.with_activation(I.tiny(name), act)
+@pytest.mark.parametrize("case", CASES, ids=_case_id)
+def test_assembly_matches_oracle(rfm, case):
+    inst = _instance(case)
+    name, act = inst.name, case[1]
     print(f"[assembly] {name} {act}", flush=True)
     plan, prob = _setup(rfm, inst)
     M, h = rfm.rfm_assemble(plan, prob)
@@ -284,13 +300,14 @@ def test_coefficients_match_oracle_back_substitution(rfm):
         assert np.all(ag[sl][a_or[sl] == 0.0] == 0.0)
 
 
-@pytest.mark.parametrize("name,act", [("poisson1d", "tanh"), ("heat3d", "tanh"),
-                                      ("poisson1d", "sigmoid"), ("poisson1d", "sin"),
-                                      ("oscillator1d", "tanh"), ("laplace2d_multiscale", "tanh")])
-def test_end_to_end_gpu_pipeline(rfm, name, act):
+@pytest.mark.parametrize("case", [("poisson1d", "tanh", 1, 0), ("heat3d", "tanh", 1, 0),
+                                  ("poisson1d", "sigmoid", 1, 0), ("poisson1d", "sin", 1, 0),
+                                  ("oscillator1d", "tanh", 1, 0), ("laplace2d_multiscale", "tanh", 1, 0),
+                                  ("oscillator1d", "tanh", 3, 8), ("poisson1d", "tanh", 5, 16)], ids=_case_id)
+def test_end_to_end_gpu_pipeline(rfm, case):
     """Each side with its own factors: report the differences, check the error metric."""
-    full = name in ("poisson1d", "oscillator1d")
-    inst = I.with_activation(I.workload(name) if full else I.tiny(name), act)
+    name, act = case[0], case[1]
+    inst = _instance(case, full=name in ("poisson1d", "oscillator1d"))
     print(f"[e2e] {name} {act}", flush=True)
     plan, prob = _setup(rfm, inst)
     M, h = rfm.rfm_assemble(plan, prob)
@@ -648,13 +665,14 @@ def test_multi_rhs_warm_start_guard_per_column(rfm):
         assert iw[b] <= 2
 
 
-@pytest.mark.parametrize("name,act", ACT_CASES)
-def test_evaluation_and_l1_error_match_oracle(rfm, name, act):
+@pytest.mark.parametrize("case", CASES, ids=_case_id)
+def test_evaluation_and_l1_error_match_oracle(rfm, case):
     """u_hat at the test grid and e_L1 (Sec. 4.2) from the GPU against the oracle's
     evaluation of the same coefficients; u_hat within 64 u times the absolute-value
     evaluation sum_j w_j sum_k |a_jk| |phi_jk| (cancellation between features is the
     rule for these coefficients)."""
-    inst = I.with_activation(I.tiny(name), act)
+    inst = _instance(case)
+    name, act = inst.name, case[1]
     print(f"[evaluate] {name} {act}", flush=True)
     rng = np.random.default_rng(21)
     a = rng.standard_normal(inst.feat_off[-1]) * 10.0 ** rng.uniform(-2, 3, inst.feat_off[-1])
@@ -678,8 +696,7 @@ def test_evaluation_and_l1_error_match_oracle(rfm, name, act):
         if r.size == 0:
             continue
         k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
-        phi, _, _ = assembly.features(xt[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1],
-                                      inst.activation)
+        phi, _, _ = assembly.block_features(inst, j, xt[r])
         W, _, _ = assembly.unnormalised_window(xt[r], inst.mu[j], inst.hw[j])
         scale[r] += (W / S[r]) * (np.abs(phi) @ np.abs(a[k0:k1]))
     if inst.ansatz is not None:
@@ -693,13 +710,14 @@ def test_evaluation_and_l1_error_match_oracle(rfm, name, act):
     assert e2 is None and torch.equal(uh2, uh)
 
 
-@pytest.mark.parametrize("name,act", ACT_CASES)
+@pytest.mark.parametrize("case", CASES, ids=_case_id)
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_low_precision_assembly_error_against_oracle(rfm, name, act, dtype):
+def test_low_precision_assembly_error_against_oracle(rfm, case, dtype):
     """The precision form's assembly (binary32 arithmetic, binary32 or bfloat16 storage):
     normwise relative error per block against the binary64 oracle, measured and reported;
     bounded by 1e-3 (binary32) and 1e-2 (bfloat16: its own rounding is 2^-9 relative)."""
-    inst = I.with_activation(I.tiny(name), act)
+    inst = _instance(case)
+    name, act = inst.name, case[1]
     plan, prob = _setup(rfm, inst)
     Ml, h = rfm.rfm_assemble_low(plan, prob, rfm.F32 if dtype == "f32" else rfm.BF16)
     M64, h64 = rfm.rfm_assemble(plan, prob)

@@ -106,6 +106,52 @@ def test_feature_derivatives_finite_difference(act):
         assert np.allclose((pp - 2 * phi + pm) / e**2, ddphi[:, :, i], atol=2e-4)
 
 
+@pytest.mark.parametrize("act", assembly.ACTIVATIONS)
+@pytest.mark.parametrize("depth", [2, 3, 5])
+def test_network_features_against_autograd(act, depth):
+    """The forward-mode derivatives of a depth-h network against reverse-mode automatic
+    differentiation (first derivatives and the diagonal of the Hessian, per feature) of the
+    plainly written network value."""
+    import torch
+    rng = np.random.default_rng(8)
+    d, H, K = 2, 6, 4
+    x = rng.uniform(0.2, 0.6, (5, d))
+    mu, hw = np.array([0.4, 0.35]), np.array([0.3, 0.25])
+    layers = [(rng.uniform(-1, 1, (H, d)), rng.uniform(-1, 1, H))]
+    layers += [(rng.uniform(-0.7, 0.7, (H, H)), rng.uniform(-1, 1, H)) for _ in range(depth - 2)]
+    wk, bk = rng.uniform(-0.7, 0.7, (K, H)), rng.uniform(-1, 1, K)
+    phi, dphi, ddphi = assembly.network_features(x, mu, hw, layers, wk, bk, act)
+    f = {"tanh": torch.tanh, "sigmoid": torch.sigmoid, "sin": torch.sin}[act]
+    T = lambda a: torch.tensor(a, dtype=torch.float64)
+
+    def net(xp, k):
+        z = (xp - T(mu)) / T(hw)
+        for W, b in layers:
+            z = f(T(W) @ z + T(b))
+        return f(T(wk[k]) @ z + T(bk[k]))
+
+    for i in range(len(x)):
+        for k in range(K):
+            xp = T(x[i])
+            g = torch.autograd.functional.jacobian(lambda v: net(v, k), xp)
+            Hs = torch.autograd.functional.hessian(lambda v: net(v, k), xp)
+            assert abs(float(net(xp, k)) - phi[i, k]) < 1e-15
+            assert np.allclose(g.numpy(), dphi[i, k], rtol=1e-12, atol=1e-13)
+            assert np.allclose(np.diag(Hs.numpy()), ddphi[i, k], rtol=1e-11, atol=1e-12)
+
+
+def test_network_without_hidden_layers_is_the_depth_one_feature():
+    rng = np.random.default_rng(9)
+    x = rng.uniform(0.1, 0.9, (7, 3))
+    mu, hw = np.array([0.5, 0.4, 0.6]), np.array([0.3, 0.2, 0.4])
+    wk, bk = rng.uniform(-1, 1, (4, 3)), rng.uniform(-1, 1, 4)
+    for act in assembly.ACTIVATIONS:
+        a = assembly.network_features(x, mu, hw, [], wk, bk, act)
+        b = assembly.features(x, mu, hw, wk, bk, act)
+        for u, v in zip(a, b):
+            assert np.allclose(u, v, rtol=1e-14, atol=1e-14)
+
+
 def test_activation_special_values():
     """Xi, Xi', Xi'' at 0 and far out: tanh (0, 1, 0), sigmoid (1/2, 1/4, 0), sin (0, 1, 0);
     sigmoid and tanh saturate with vanishing derivatives; sin(pi/2) = 1, sin''(pi/2) = -1."""
@@ -161,9 +207,12 @@ def _fd_operator(inst, a, xr, op):
                                       ("helmholtz2d_uneven", "tanh"), ("poisson1d", "sigmoid"),
                                       ("poisson2d", "sin"), ("heat3d", "sigmoid"),
                                       ("helmholtz2d_uneven", "sin"), ("oscillator1d", "tanh"),
-                                      ("laplace2d_multiscale", "tanh"), ("laplace2d_multiscale", "sin")])
+                                      ("laplace2d_multiscale", "tanh"), ("laplace2d_multiscale", "sin"),
+                                      ("poisson2d", "tanh-h3"), ("oscillator1d", "sin-h5"),
+                                      ("heat3d", "tanh-h3")])
 def test_assembled_rows_match_finite_difference_operator(name, act):
-    inst = I.with_activation(I.tiny(name), act)
+    act, _, depth = act.partition("-h")
+    inst = I.with_depth(I.with_activation(I.tiny(name), act), int(depth or 1), 8)
     rows, blocks, h = assembly.assemble(inst)
     M = assembly.global_dense(inst, rows, blocks)
     rng = np.random.default_rng(7)
@@ -217,13 +266,18 @@ def test_incidence_strict_support_and_cover_bound():
                                       ("helmholtz2d_uneven", "tanh"), ("poisson1d", "sigmoid"),
                                       ("heat3d", "sin"), ("helmholtz2d_uneven", "sigmoid"),
                                       ("poisson2d", "sin"), ("oscillator1d", "tanh"),
-                                      ("laplace2d_multiscale", "tanh")])
+                                      ("laplace2d_multiscale", "tanh"), ("poisson1d", "tanh-h3"),
+                                      ("heat3d", "sigmoid-h3"), ("laplace2d_multiscale", "sin-h5")])
 def test_entry_error_scale_bounds_binary64_rounding(name, act):
     """The binary64 assembly sits within a few u * E of an extended-precision evaluation,
     E the absolute-value evaluation used to size the GPU/oracle tolerance."""
-    inst = I.with_activation(I.tiny(name), act)
+    act, _, depth = act.partition("-h")
+    make = lambda: I.with_depth(I.with_activation(I.tiny(name), act), int(depth or 1), 8)
+    inst = make()
     rows, blocks, _ = assembly.assemble(inst)
-    ext = I.with_activation(I.tiny(name), act)
+    ext = make()
+    if ext.net is not None:
+        ext.net = ext.net.astype(np.longdouble)
     for k in ("x", "mu", "hw", "w", "b", "weight", "rhs"):
         setattr(ext, k, getattr(inst, k).astype(np.longdouble))
     _, blocks_ext, _ = assembly.assemble(ext)
