@@ -248,7 +248,7 @@ def paper_problems_study(args):
             out.append(flat[o:o + m * int(c)].reshape(int(c), m).T)
         return out
 
-    for name in ("oscillator1d", "laplace2d_multiscale"):
+    for name in ("oscillator1d", "laplace2d_multiscale", "wave2d"):
         base = I.workload(name, seed=args.seed)
         rows = []
         kM = {}
@@ -271,7 +271,9 @@ def paper_problems_study(args):
             xt = inst.test_points()
             tplan, xd = rfm.evaluation_points(inst, xt)
             gt = rfm.evaluation_ansatz(inst, xt)
-            ue = torch.from_numpy(inst.exact(xt)).to(dev)
+            # the wave problem has no closed form (the paper compares against a finite-difference
+            # solver): its rows report the relative residual only
+            ue = torch.from_numpy(inst.exact(xt)).to(dev) if inst.exact is not None else None
             errs = {}
             for it in checkpoints:
                 torch.cuda.synchronize()
@@ -280,9 +282,10 @@ def paper_problems_study(args):
                                              use_graph=1)
                 torch.cuda.synchronize()
                 lsqr_s = time.perf_counter() - t0
-                a = rfm.rfm_coefficients(plan, fact, y)
-                _, e = rfm.rfm_evaluate(tplan, xd, prob, a, u_exact=ue, ansatz=gt)
-                errs[str(it)] = e
+                if ue is not None:
+                    a = rfm.rfm_coefficients(plan, fact, y)
+                    _, e = rfm.rfm_evaluate(tplan, xd, prob, a, u_exact=ue, ansatz=gt)
+                    errs[str(it)] = e
             ho = plan.host
             Mb = host_blocks(ho, M.cpu().numpy(), K)
             kp = fact["kept"].cpu().numpy()
@@ -296,11 +299,13 @@ def paper_problems_study(args):
             row = {"activation": act, "tau": tau, "depth": depth, "kept": kept, "columns": ncols,
                    "drop_pct": 100.0 * (1 - kept / ncols), "kappa_M": kM[key], "kappa_M_hat": k_hat,
                    "kappa_M_hat_S_inv": k_pre, "filter_ms": filt_ms, "lsqr_10k_s": lsqr_s,
-                   "iters": int(info.iters), "e_l1": errs, "e_l1_min": min(errs.values())}
+                   "iters": int(info.iters), "relres": float(info.relres), "e_l1": errs or None,
+                   "e_l1_min": min(errs.values()) if errs else None}
             rows.append(row)
             print(f"[paper problems] {name} {act} h={depth} sigma={tau:g}: dropped {row['drop_pct']:.0f} %, kappa "
                   f"M {kM[key]:.1e}, M_hat {k_hat:.1e}, M_hat S^-1 {k_pre:.1e}; filter {filt_ms:.2f} ms, "
-                  f"10k iterations {lsqr_s:.2f} s; e_L1 min {row['e_l1_min']:.2e}", file=sys.stderr, flush=True)
+                  f"10k iterations {lsqr_s:.2f} s; relres {row['relres']:.2e}"
+                  + (f", e_L1 min {row['e_l1_min']:.2e}" if errs else ""), file=sys.stderr, flush=True)
             del M, fact
         out["problems"][name] = {"N": base.N, "J": base.J, "columns": int(base.feat_off[-1]), "variants": rows}
         torch.cuda.empty_cache()

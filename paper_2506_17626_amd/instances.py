@@ -100,6 +100,8 @@ class Instance:
     depth: int = 1          # h of the subdomain networks; > 1: hidden layers of width `hidden`
     hidden: int = 0
     net: np.ndarray | None = None  # [J, H d + H + (h-2)(H H + H)] hidden parameters per subdomain
+    domain: np.ndarray | None = None  # [d, 2] box (lo, hi) per dim; None = the unit cube
+    offset: object = None   # callable x[n,d] -> [n]: additive part of the trial solution
 
     @property
     def N(self) -> int:
@@ -113,7 +115,10 @@ class Instance:
         n = self.test_grid if n is None else n
         g = (np.arange(n) + 0.5) / n
         mesh = np.meshgrid(*([g] * self.d), indexing="ij")
-        return np.stack([m.ravel() for m in mesh], axis=1)
+        x = np.stack([m.ravel() for m in mesh], axis=1)
+        if self.domain is not None:
+            x = self.domain[:, 0] + x * (self.domain[:, 1] - self.domain[:, 0])
+        return x
 
 
 # ---------------------------------------------------------------- geometry
@@ -145,12 +150,14 @@ def _features(rng: Rng, K: np.ndarray, d: int):
     return feat_off, w, b
 
 
-def _paper_geometry(d: int, S: int, delta: float):
-    """eq. dd on [0,1]^d: centres (j-1)/(S-1) per dim, half-width delta / (2 (S-1))."""
-    centres_1d = np.arange(S) / (S - 1)
+def _paper_geometry(d: int, S: int, delta: float, box=None):
+    """eq. dd on a box (default [0,1]^d): centres a + (b-a)(j-1)/(S-1) per dim, half-width
+    (b-a) delta / (2 (S-1))."""
+    box = np.array([[0.0, 1.0]] * d) if box is None else np.asarray(box, dtype=np.float64)
     idx = np.stack(np.meshgrid(*([np.arange(S)] * d), indexing="ij"), axis=-1).reshape(-1, d)
-    mu = centres_1d[idx]
-    hw = np.full_like(mu, delta / (2.0 * (S - 1)))
+    span = box[:, 1] - box[:, 0]
+    mu = box[None, :, 0] + span[None, :] * idx / (S - 1)
+    hw = np.broadcast_to(span * delta / (2.0 * (S - 1)), mu.shape).copy()
     return mu, hw
 
 
@@ -419,6 +426,74 @@ def laplace2d_multiscale(S=16, K=16, n=3, delta=2.9, seed=0, name="laplace2d_mul
                     meta=dict(S=S, K=K, n=n, delta=delta, seed=seed))
 
 
+def _tanh_pair(a: float, lo: float, hi: float, x: np.ndarray):
+    """F(x) = tanh(a (x - lo)) tanh(a (hi - x)), zero at both ends, and F', F''."""
+    p, q = np.tanh(a * (x - lo)), np.tanh(a * (hi - x))
+    p1, q1 = a * (1.0 - p * p), -a * (1.0 - q * q)
+    p2, q2 = -2.0 * a * p * p1, 2.0 * a * q * q1
+    return p * q, p1 * q + p * q1, p2 * q + 2.0 * p1 * q1 + p * q2
+
+
+def wave2d(S=8, K=8, lam=0.2, c=1.0, delta=2.9, seed=0, name="wave2d") -> Instance:
+    """Acoustic wave in (2+1)D (Section 5.1): Laplace_x u - c^-2 u_tt = 0 on [-1,1]^2 x [0,1],
+    u = 0 on the spatial boundary, u(x,0) = exp(-|x|^2 / (2 lam^2)), u_t(x,0) = 0, through the
+    hard-constraint trial solution u~ = B(x) (G(x,t) + tanh^2(t/tau) u_hat) with
+    B = prod_i tanh((1 + x_i)/d) tanh((1 - x_i)/d), G = exp(-((0.6 t/tau)^2 + |x|^2/lam^2)/2),
+    d = lam/2.5, tau = lam/(2.5 c).  Linear in the coefficients: u~ = g u_hat + A with the
+    factor g = B tanh^2(t/tau) and the additive part A = B G, whose operator image goes to the
+    right-hand side (rhs = -Op[A]).  No closed-form solution (the paper compares against a
+    finite-difference solver).  Points: (S ceil(K^(1/3)))^3 on the cell-centred grid (g = 0 on
+    the spatial boundary and at t = 0)."""
+    d3 = 3
+    rng = Rng(seed)
+    box = np.array([[-1.0, 1.0], [-1.0, 1.0], [0.0, 1.0]])
+    mu, hw = _paper_geometry(d3, S, delta, box)
+    feat_off, w, b = _features(rng, np.full(S**3, K, dtype=np.int64), d3)
+    dl, tau = lam / 2.5, lam / (2.5 * c)
+    kap = 0.18 / tau**2                       # (0.6/tau)^2 / 2
+
+    def spatial(s):
+        """P = F e with e = exp(-s^2 / (2 lam^2)): values, first and second derivatives."""
+        F, F1, F2 = _tanh_pair(1.0 / dl, -1.0, 1.0, s)
+        e = np.exp(-s * s / (2 * lam**2))
+        e1 = -s / lam**2 * e
+        e2 = (s * s / lam**4 - 1.0 / lam**2) * e
+        return (F, F1, F2), (F * e, F1 * e + F * e1, F2 * e + 2 * F1 * e1 + F * e2)
+
+    def ansatz(x):
+        (F0, F01, F02), _ = spatial(x[:, 0])
+        (F1, F11, F12), _ = spatial(x[:, 1])
+        q = np.tanh(x[:, 2] / tau)
+        q1 = (1.0 - q * q) / tau
+        Q, Q1, Q2 = q * q, 2 * q * q1, 2 * q1 * q1 - 4 * q * q * q1 / tau
+        return np.stack([F0 * F1 * Q, F01 * F1 * Q, F0 * F11 * Q, F0 * F1 * Q1,
+                         F02 * F1 * Q, F0 * F12 * Q, F0 * F1 * Q2], axis=1)
+
+    def offset(x):
+        _, (P0, _, _) = spatial(x[:, 0])
+        _, (P1, _, _) = spatial(x[:, 1])
+        return P0 * P1 * np.exp(-kap * x[:, 2] ** 2)
+
+    def offset_image(x):
+        """Laplace_x A - c^-2 A_tt for A = P(x1) P(x2) T(t), T = exp(-kap t^2)."""
+        _, (P0, _, P02) = spatial(x[:, 0])
+        _, (P1, _, P12) = spatial(x[:, 1])
+        t = x[:, 2]
+        T = np.exp(-kap * t * t)
+        T2 = (4 * kap * kap * t * t - 2 * kap) * T
+        return P02 * P1 * T + P0 * P12 * T - P0 * P1 * T2 / c**2
+
+    n = S * math.ceil(round(K ** (1.0 / 3.0), 12))
+    xi = box[:, 0] + _full_grid(d3, n, ends=False) * (box[:, 1] - box[:, 0])
+    NI = xi.shape[0]
+    rowop = np.full(NI, OP_COEF + 0, dtype=np.int32)
+    weight = np.full(NI, 1 / math.sqrt(NI))
+    opcoef = np.array([[0.0, 0.0, 0.0, 0.0, 1.0, 1.0, -1.0 / c**2]])
+    return Instance(name, d3, S**3, mu, hw, feat_off, w, b, xi, rowop, weight, -offset_image(xi),
+                    test_grid=4 * S, opcoef=opcoef, ansatz=ansatz, domain=box, offset=offset,
+                    meta=dict(S=S, K=K, lam=lam, c=c, delta=delta, seed=seed))
+
+
 def workload(name: str, seed: int = 0) -> Instance:
     """The five named workloads at their full sizes."""
     if name == "poisson1d":       # 20 subdomains, 64 features, 100 points each
@@ -435,6 +510,8 @@ def workload(name: str, seed: int = 0) -> Instance:
         return oscillator1d(seed=seed)
     if name == "laplace2d_multiscale":  # the paper's Laplacian baseline: S=16, K=16, n=3
         return laplace2d_multiscale(seed=seed)
+    if name == "wave2d":              # the paper's wave baseline: S=8, K=8, lambda=0.2
+        return wave2d(seed=seed)
     raise KeyError(name)
 
 
@@ -483,4 +560,6 @@ def tiny(name: str, seed: int = 0) -> Instance:
         return oscillator1d(S=6, K=8, omega0=15.0, seed=seed, name="oscillator1d_tiny")
     if name == "laplace2d_multiscale":
         return laplace2d_multiscale(S=4, K=9, n=2, seed=seed, name="laplace2d_multiscale_tiny")
+    if name == "wave2d":
+        return wave2d(S=3, K=8, lam=0.5, seed=seed, name="wave2d_tiny")
     raise KeyError(name)

@@ -209,7 +209,7 @@ def _fd_operator(inst, a, xr, op):
                                       ("helmholtz2d_uneven", "sin"), ("oscillator1d", "tanh"),
                                       ("laplace2d_multiscale", "tanh"), ("laplace2d_multiscale", "sin"),
                                       ("poisson2d", "tanh-h3"), ("oscillator1d", "sin-h5"),
-                                      ("heat3d", "tanh-h3")])
+                                      ("heat3d", "tanh-h3"), ("wave2d", "tanh"), ("wave2d", "sin-h3")])
 def test_assembled_rows_match_finite_difference_operator(name, act):
     act, _, depth = act.partition("-h")
     inst = I.with_depth(I.with_activation(I.tiny(name), act), int(depth or 1), 8)
@@ -267,7 +267,8 @@ def test_incidence_strict_support_and_cover_bound():
                                       ("heat3d", "sin"), ("helmholtz2d_uneven", "sigmoid"),
                                       ("poisson2d", "sin"), ("oscillator1d", "tanh"),
                                       ("laplace2d_multiscale", "tanh"), ("poisson1d", "tanh-h3"),
-                                      ("heat3d", "sigmoid-h3"), ("laplace2d_multiscale", "sin-h5")])
+                                      ("heat3d", "sigmoid-h3"), ("laplace2d_multiscale", "sin-h5"),
+                                      ("wave2d", "tanh")])
 def test_entry_error_scale_bounds_binary64_rounding(name, act):
     """The binary64 assembly sits within a few u * E of an extended-precision evaluation,
     E the absolute-value evaluation used to size the GPU/oracle tolerance."""

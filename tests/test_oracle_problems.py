@@ -100,3 +100,69 @@ def test_oracle_solves_the_paper_problems(name, bound):
     sol = solve.solve(inst, tau=1e-8, atol=1e-12, btol=1e-12, maxit=10000)
     e = solve.l1_error(inst, sol.a)
     assert e < bound, e
+
+
+def test_wave_trial_solution_meets_the_initial_and_boundary_conditions():
+    """u~ = g u_hat + A: g and g_t vanish at t = 0 and g on the spatial boundary, so
+    u~(x, 0) = A(x, 0), which is the Gaussian source inside the box, with A_t(x, 0) = 0;
+    A vanishes on the spatial boundary."""
+    inst = I.workload("wave2d")
+    lam = inst.meta["lam"]
+    rng = np.random.default_rng(6)
+    xs = rng.uniform(-0.5, 0.5, (50, 2))
+    x0 = np.concatenate([xs, np.zeros((50, 1))], axis=1)
+    G = inst.ansatz(x0)
+    assert np.all(G[:, 0] == 0.0) and np.all(G[:, 3] == 0.0)       # g(x,0) = g_t(x,0) = 0
+    src = np.exp(-np.sum(xs * xs, axis=1) / (2 * lam**2))
+    assert np.max(np.abs(inst.offset(x0) - src)) < 1e-4             # B = 1 - O(1e-5) inside
+    e = 1e-5
+    xp, xm = x0.copy(), x0.copy()
+    xp[:, 2] += e
+    xm[:, 2] -= e
+    assert np.max(np.abs(inst.offset(xp) - inst.offset(xm))) / (2 * e) < 1e-8
+    edge = np.array([[-1.0, 0.3, 0.5], [1.0, -0.2, 0.1], [0.4, -1.0, 0.9], [0.0, 1.0, 0.3]])
+    assert np.all(inst.ansatz(edge)[:, 0] == 0.0) and np.all(inst.offset(edge) == 0.0)
+
+
+def test_wave_rhs_is_minus_the_operator_image_of_the_additive_part():
+    inst = I.tiny("wave2d")
+    c2 = -1.0 / inst.opcoef[0, 6]
+    x = inst.x[:: 7]
+    e = 1e-4
+    img = np.zeros(len(x))
+    for i, coef in ((0, 1.0), (1, 1.0), (2, -1.0 / c2)):
+        xp, xm = x.copy(), x.copy()
+        xp[:, i] += e
+        xm[:, i] -= e
+        img += coef * (inst.offset(xp) - 2 * inst.offset(x) + inst.offset(xm)) / e**2
+    rhs = inst.rhs[:: 7]
+    assert np.allclose(rhs, -img, rtol=1e-5, atol=1e-5 * np.abs(img).max())
+    assert inst.opcoef.tolist() == [[0.0, 0.0, 0.0, 0.0, 1.0, 1.0, -1.0]]
+
+
+@pytest.mark.parametrize("name", ["laplace2d_multiscale", "wave2d"])
+def test_every_ansatz_factor_against_finite_differences(name):
+    inst = I.tiny(name)
+    rng = np.random.default_rng(10)
+    lo, hi = (inst.domain[:, 0], inst.domain[:, 1]) if inst.domain is not None else (0.0, 1.0)
+    x = lo + (hi - lo) * rng.uniform(0.05, 0.95, (30, inst.d))
+    G = inst.ansatz(x)
+    d = inst.d
+    e = 1e-5
+    for i in range(d):
+        xp, xm = x.copy(), x.copy()
+        xp[:, i] += e
+        xm[:, i] -= e
+        gp, gm = inst.ansatz(xp)[:, 0], inst.ansatz(xm)[:, 0]
+        scale = np.abs(G[:, 1 + d + i]).max() + np.abs(G[:, 1 + i]).max()
+        assert np.allclose((gp - gm) / (2 * e), G[:, 1 + i], rtol=1e-6, atol=1e-7 * scale)
+        assert np.allclose((gp - 2 * G[:, 0] + gm) / e**2, G[:, 1 + d + i], rtol=1e-3, atol=1e-4 * scale)
+
+
+def test_box_geometry_of_eq_dd():
+    inst = I.workload("wave2d")
+    assert np.allclose(np.unique(inst.mu[:, 0]), -1 + 2 * np.arange(8) / 7)
+    assert np.allclose(np.unique(inst.mu[:, 2]), np.arange(8) / 7)
+    assert np.allclose(inst.hw[0], [2 * 2.9 / 14, 2 * 2.9 / 14, 2.9 / 14])
+    xt = inst.test_points()
+    assert xt.shape == (32**3, 3) and xt[:, :2].min() > -1 and xt[:, 2].max() < 1
