@@ -307,8 +307,66 @@ def paper_problems_study(args):
                   f"10k iterations {lsqr_s:.2f} s; relres {row['relres']:.2e}"
                   + (f", e_L1 min {row['e_l1_min']:.2e}" if errs else ""), file=sys.stderr, flush=True)
             del M, fact
-        out["problems"][name] = {"N": base.N, "J": base.J, "columns": int(base.feat_off[-1]), "variants": rows}
+        # the strong RRQR variant of the filter (Gu-Eisenstat exchanges, f = 2) at the sigmas
+        # that drop columns: exchanges made, time, and the accuracy reached
+        strong = []
+        for tau in (1e-6, 1e-4, 1e-2):
+            inst = base
+            plan = rfm.plan_instance(inst)
+            prob = rfm.problem_tensors(inst)
+            M, h = rfm.rfm_assemble(plan, prob)
+            rfm.rfm_rrqr_strong(plan, M, tau, f=2.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fact, swaps, rounds = rfm.rfm_rrqr_strong(plan, M, tau, f=2.0)
+            torch.cuda.synchronize()
+            st_ms = 1e3 * (time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            plain = rfm.rfm_rrqr_filter(plan, M, tau, tune=rfm.Tuning(rrqr_algo=1))
+            torch.cuda.synchronize()
+            plain_ms = 1e3 * (time.perf_counter() - t0)
+            xt = inst.test_points()
+            tplan, xd = rfm.evaluation_points(inst, xt)
+            gt = rfm.evaluation_ansatz(inst, xt)
+            ue = torch.from_numpy(inst.exact(xt)).to(dev) if inst.exact is not None else None
+            y, info = rfm.rfm_lsqr_solve(plan, fact, h, atol=0.0, btol=0.0, maxit=10000, check_every=256, use_graph=1)
+            e = None
+            if ue is not None:
+                _, e = rfm.rfm_evaluate(tplan, xd, prob, rfm.rfm_coefficients(plan, fact, y), u_exact=ue, ansatz=gt)
+            kept = int(fact["rank"].sum())
+            strong.append({"tau": tau, "f": 2.0, "kept": kept, "swaps": swaps, "rounds": rounds,
+                           "strong_ms": st_ms, "direct_filter_ms": plain_ms, "relres": float(info.relres),
+                           "e_l1_10k": e, "max_rho": float(fact["rho"].max())})
+            print(f"[paper problems] {name} strong f=2 sigma={tau:g}: kept {kept}, {swaps} exchanges in {rounds} "
+                  f"rounds, {st_ms:.2f} ms (direct filter {plain_ms:.2f} ms), relres {info.relres:.2e}"
+                  + (f", e_L1 {e:.2e}" if e is not None else ""), file=sys.stderr, flush=True)
+            del M, fact, plain
+        out["problems"][name] = {"N": base.N, "J": base.J, "columns": int(base.feat_off[-1]), "variants": rows,
+                                 "strong": strong}
         torch.cuda.empty_cache()
+    # the strong variant on the 2D workload's blocks
+    inst = I.workload("poisson2d", seed=args.seed)
+    plan = rfm.plan_instance(inst)
+    prob = rfm.problem_tensors(inst)
+    M, h = rfm.rfm_assemble(plan, prob)
+    big = []
+    for tau in (1e-12, 1e-8):
+        rfm.rfm_rrqr_strong(plan, M, tau, f=2.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fact, swaps, rounds = rfm.rfm_rrqr_strong(plan, M, tau, f=2.0)
+        torch.cuda.synchronize()
+        st_ms = 1e3 * (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        rfm.rfm_rrqr_filter(plan, M, tau, tune=rfm.Tuning(rrqr_algo=1))
+        torch.cuda.synchronize()
+        plain_ms = 1e3 * (time.perf_counter() - t0)
+        big.append({"tau": tau, "kept": int(fact["rank"].sum()), "swaps": swaps, "rounds": rounds,
+                    "strong_ms": st_ms, "direct_filter_ms": plain_ms, "max_rho": float(fact["rho"].max())})
+        print(f"[paper problems] poisson2d workload strong f=2 tau={tau:g}: kept {big[-1]['kept']}, {swaps} exchanges, "
+              f"{st_ms:.2f} ms (direct filter {plain_ms:.2f} ms), max rho {big[-1]['max_rho']:.2f}",
+              file=sys.stderr, flush=True)
+    out["poisson2d_strong"] = big
     print(json.dumps(out), flush=True)
 
 

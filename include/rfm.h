@@ -379,6 +379,27 @@ rfm_status rfm_coefficients(const rfm_layout *L, const int32_t *rank, const int3
 /* Bytes of device workspace rfm_evaluate needs for a test-point layout. */
 size_t rfm_evaluate_ws_bytes(const rfm_layout *L);
 
+/* Strong rank-revealing variant of the filter (Section 2.3: the factorisation may be any
+ * rank-revealing QR, strong RRQR of Gu and Eisenstat among them).  The rank r_j of every block
+ * is the sigma-filter's (column-pivoted QR stopped at |R_ss| <= tau |R_00|, direct
+ * factorisation); then, per block, with R = [A B; 0 C] in the current pivot order (A = R_hat),
+ *   rho_iq = (A^-1 B)_iq^2 + ||C e_q||^2 ||e_i^T A^-1||^2,
+ * and while max rho > f^2 the pair (i, q) of the maximum is exchanged (kept column i for
+ * trailing column q; ties to the smaller i, then q) and the block refactored in its new order
+ * with the same rank, at most max_rounds rounds over all blocks (each round swaps once in
+ * every block that needs it; |det A| grows by more than f per swap, so the loop ends).  On
+ * return every block satisfies max rho <= f^2 unless stats[1] == max_rounds, and then
+ * sigma_i(A) >= sigma_i(M_j) / sqrt(1 + f^2 r (n - r)) and
+ * sigma_q(C) <= sigma_(r+q)(M_j) sqrt(1 + f^2 r (n - r)) (Gu and Eisenstat 1996).
+ * Outputs as rfm_rrqr_filter (rank, kept in pivot order, R_hat, Q_hat; no ratios), plus
+ * rho device [J]: the largest rho of the last test per block (0 where r is 0 or n_j), and
+ * stats host [2]: total swaps, rounds taken.  f > 1.  Sync (one host read per round).
+ * ws: rfm_rrqr_strong_ws_bytes(L) device bytes.  Needs max_rows <= 3072. */
+size_t rfm_rrqr_strong_ws_bytes(const rfm_layout *L);
+rfm_status rfm_rrqr_strong(const rfm_layout *L, const double *M, double tau, double f, int32_t max_rounds,
+                           int32_t *rank, int32_t *kept, double *R, double *Q, double *rho, int32_t *stats,
+                           void *ws, size_t ws_bytes, void *stream);
+
 /* Solution at test points and its error (Sec. 4.2 performance evaluation; eq. elm_solution
  * with the windows of eq. used_window_function_nd): u_hat(x_t) = sum over the subdomains j
  * covering x_t (strict |x - mu| < hw) of w_j(x_t) sum_k a_(j,k) Xi(w_(j,k) . (x_t - mu_j)/hw_j

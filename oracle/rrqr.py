@@ -101,3 +101,57 @@ def qrcp_filter(Mj: np.ndarray, tau: float) -> RRQRResult:
 def filter_blocks(blocks, tau: float):
     """Algorithm 1: the sigma-RRQR filter applied independently to every block."""
     return [qrcp_filter(Mj, tau) for Mj in blocks]
+
+
+# ---------------------------------------------------------------- strong RRQR
+# Gu and Eisenstat (1996): for a fixed rank r, with R = [A B; 0 C] the triangular factor of
+# M_j in pivot order, the factorisation is strong with parameter f > 1 when every
+#   rho_iq = (A^-1 B)_iq^2 + (gamma_q / omega_i)^2 <= f^2,
+# gamma_q = ||C e_q|| (the trailing column norms) and 1/omega_i = ||e_i^T A^-1|| (the row norms
+# of A^-1).  While it is not, exchanging kept column i for trailing column q at the largest
+# rho multiplies |det A| by sqrt(rho) > f, so the exchanges end.  The rank is the
+# sigma-filter's (Section 2.3 names strong RRQR as one admissible rank-revealing QR).
+
+def strong_measure(Mj: np.ndarray, perm: np.ndarray, r: int):
+    """rho [r, n-r] of the pivot order perm at rank r, from a fresh QR of the permuted block."""
+    m, n = Mj.shape
+    Rf = np.linalg.qr(np.asarray(Mj, dtype=np.float64)[:, perm], mode="r")   # [min(m,n), n]
+    A, B, C = Rf[:r, :r], Rf[:r, r:], Rf[r:, r:]
+    Ainv = np.linalg.solve(A, np.eye(r))
+    W = Ainv @ B
+    gam2 = np.sum(C * C, axis=0) if C.shape[0] else np.zeros(n - r)
+    om2 = np.sum(Ainv * Ainv, axis=1)
+    return W * W + gam2[None, :] * om2[:, None]
+
+
+def _argmax_first(rho: np.ndarray):
+    """Position of the largest entry, ties to the smaller row, then column."""
+    best = rho.max()
+    i, q = np.argwhere(rho == best)[0]
+    return int(i), int(q), float(best)
+
+
+def strong_filter(Mj: np.ndarray, tau: float, f: float = 2.0, max_rounds: int = 32):
+    """The sigma-filter's rank with Gu-Eisenstat exchanges; returns (RRQRResult of the final
+    order, swaps, largest rho of the last test)."""
+    base = qrcp_filter(Mj, tau)
+    m, n = np.asarray(Mj).shape
+    r, perm = base.rank, base.perm.copy()
+    swaps, last = 0, 0.0
+    for _ in range(max_rounds):
+        if r == 0 or r >= n:
+            last = 0.0
+            break
+        rho = strong_measure(Mj, perm, r)
+        i, q, last = _argmax_first(rho)
+        if last <= f * f:
+            break
+        perm[[i, r + q]] = perm[[r + q, i]]
+        swaps += 1
+    if swaps == 0:
+        return base, 0, last
+    Qf, Rf = np.linalg.qr(np.asarray(Mj, dtype=np.float64)[:, perm[:r]])
+    sgn = np.where(np.diag(Rf) < 0, -1.0, 1.0)
+    res = RRQRResult(r, perm[:r].copy(), perm, sgn[:, None] * Rf, Qf * sgn[None, :],
+                     np.array([]), np.array([]))
+    return res, swaps, last

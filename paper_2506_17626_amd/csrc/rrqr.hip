@@ -37,6 +37,14 @@ struct Lds {
   int *ired;       // [64]
 };
 
+// The strong variant's additions (all null for the plain filter): the full pivot order out,
+// a forced pivot order in (with the number of steps to take), see rfm_rrqr_strong.
+struct StrongIO {
+  int32_t *perm_out;          // [ncols] position k of block j -> local feature id
+  const int32_t *force;       // [ncols] pivot order to follow instead of the norm rule
+  const int32_t *force_rank;  // [J] steps to take under force
+};
+
 // Wave argmax with tie-break on the smaller id; all lanes get the winner.
 __device__ __forceinline__ void wave_argmax(double &best, int &bid, int &bk) {
 #pragma unroll
@@ -57,7 +65,7 @@ template <int T, int NT>
 __device__ void rrqr_one(const rfm_layout &L, const double *__restrict__ M, double tau,
                          int32_t *__restrict__ rank_out, int32_t *__restrict__ kept,
                          double *__restrict__ Rout, double *__restrict__ Q,
-                         double *__restrict__ ratios, const int j) {
+                         double *__restrict__ ratios, const int j, const StrongIO sio) {
   constexpr int NW = NT / kWave;
   extern __shared__ double lds_raw[];
   __syncthreads();  // a persistent workgroup reuses the LDS of its previous block
@@ -100,16 +108,23 @@ __device__ void rrqr_one(const rfm_layout &L, const double *__restrict__ M, doub
   __syncthreads();
 
   const int steps = min(m, n);
+  const int frank = sio.force ? sio.force_rank[j] : steps;
   int r = steps;
   double ref = 0.0;
   for (int s = 0; s < steps; ++s) {
-    // ---- pivot: largest trailing norm, ties to the smallest feature id
+    if (s >= frank) {  // forced order: the given number of steps
+      r = s;
+      break;
+    }
+    // ---- pivot: largest trailing norm, ties to the smallest feature id (or, under a forced
+    // order, the position holding the given feature)
+    const int want = sio.force ? sio.force[f0 + s] : -1;
     double best = -1.0;
     int bid = INT_MAX, bk = -1;
     for (int k = s + tid; k < n; k += NT) {
       const double cv = s_.c[k];
       const int id = s_.perm[k];
-      if (cv > best || (cv == best && id < bid)) {
+      if (want >= 0 ? id == want : (cv > best || (cv == best && id < bid))) {
         best = cv;
         bid = id;
         bk = k;
@@ -139,8 +154,12 @@ __device__ void rrqr_one(const rfm_layout &L, const double *__restrict__ M, doub
       r = 0;
       break;
     }
+    if (bk < 0) {  // a forced feature not among the remaining positions: stop here
+      r = s;
+      break;
+    }
     if (tid == 0 && ratios) ratios[f0 + s] = best / ref;
-    if (best <= tau * ref) {
+    if (!sio.force && best <= tau * ref) {
       r = s;
       break;
     }
@@ -237,6 +256,13 @@ __device__ void rrqr_one(const rfm_layout &L, const double *__restrict__ M, doub
   for (int k = tid; k < n; k += NT) kept[f0 + k] = (k < r) ? s_.perm[k] : -1;
   for (int k = tid; k < r; k += NT) s_.dsgn[k] = (A[(int64_t)k * m + k] < 0.0) ? -1.0 : 1.0;
   __syncthreads();
+  if (sio.perm_out) {
+    // the strong variant reads the trailing columns [B; C] left in the slot: their first r
+    // rows take the sign normalisation of R_hat's rows, so B stays consistent with R_hat
+    for (int k = tid; k < n; k += NT) sio.perm_out[f0 + k] = s_.perm[k];
+    for (int k = r + wid; k < n; k += NW)
+      for (int i = lane; i < r; i += kWave) A[(int64_t)k * m + i] *= s_.dsgn[i];
+  }
   for (int k = wid; k < r; k += NW)
     for (int i = lane; i < r; i += kWave)
       R[(int64_t)k * n + i] = (i <= k) ? s_.dsgn[i] * A[(int64_t)k * m + i] : 0.0;
@@ -297,9 +323,10 @@ template <int T, int NT>
 __global__ __launch_bounds__(NT) void rrqr_block(rfm_layout L, const double *__restrict__ M, double tau,
                                                  int32_t *__restrict__ rank_out, int32_t *__restrict__ kept,
                                                  double *__restrict__ Rout, double *__restrict__ Q,
-                                                 double *__restrict__ ratios, const int32_t *__restrict__ order) {
+                                                 double *__restrict__ ratios, const int32_t *__restrict__ order,
+                                                 const StrongIO sio) {
   const int b = blockIdx.x;
-  rrqr_one<T, NT>(L, M, tau, rank_out, kept, Rout, Q, ratios, order ? order[b] : b);
+  rrqr_one<T, NT>(L, M, tau, rank_out, kept, Rout, Q, ratios, order ? order[b] : b, sio);
 }
 
 // Persistent form: a fixed grid whose workgroups take blocks from a shared counter in the
@@ -318,7 +345,7 @@ __global__ __launch_bounds__(NT) void rrqr_persistent(rfm_layout L, const double
     const int b = next;
     __syncthreads();  // every thread has read `next` before thread 0 takes the next block
     if (b >= L.J) return;
-    rrqr_one<T, NT>(L, M, tau, rank_out, kept, Rout, Q, ratios, order ? order[b] : b);
+    rrqr_one<T, NT>(L, M, tau, rank_out, kept, Rout, Q, ratios, order ? order[b] : b, StrongIO{});
   }
 }
 
@@ -334,6 +361,7 @@ struct Launch {
   unsigned *queue;
   int persistent, wgs_per_cu;
   hipStream_t st;
+  StrongIO sio;
 };
 
 template <int T, int NT>
@@ -347,7 +375,7 @@ rfm_status launch_rrqr(const Launch &a) {
     auto kern = rrqr_block<T, NT>;
     RFM_HIP_TRY(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3(L->J), dim3(NT), lds, a.st, *L, a.M, a.tau, a.rank, a.kept, a.R, a.Q,
-                       a.ratios, a.order);
+                       a.ratios, a.order, a.sio);
   } else {
     int dev = 0, cus = 0;
     RFM_HIP_TRY(hipGetDevice(&dev));
@@ -386,6 +414,109 @@ rfm_status dispatch(const Launch &a, int threads) {
   if (mr <= 2048) return pick_threads<32>(a, threads);
   if (mr <= 3072) return pick_threads<48>(a, threads);
   return fail(RFM_EUNSUPPORTED, "rfm_rrqr_filter: max_rows > 3072");
+}
+
+// ---------------------------------------------------------------- strong RRQR swap test
+// For block j with 0 < r < n after a factorisation that left R_hat (r x r, positive diagonal)
+// in the R slot and the trailing columns [B; C] (sign-consistent with R_hat) in the Q slot,
+// in position order perm:
+//   X = R_hat^-1 (column c by back-substitution, one thread per column, into the block's R-sized
+//   slot of the workspace), 1/omega_i^2 = sum_c X_ic^2, W = X B, gamma_q = ||C e_q||, and
+//   rho_iq = W_iq^2 + gamma_q^2 / omega_i^2.
+// The largest rho (ties: smaller i, then smaller q) is the candidate swap of Gu and
+// Eisenstat's strong RRQR; if it exceeds f^2 the block's next pivot order is perm with
+// positions i and r + q exchanged (and the swap counter is raised), else perm itself.
+constexpr int kStrongThreads = 256;
+
+__global__ __launch_bounds__(kStrongThreads) void strong_check(rfm_layout L, const int32_t *__restrict__ rank,
+                                                               const double *__restrict__ Rout,
+                                                               const double *__restrict__ Q,
+                                                               const int32_t *__restrict__ perm, double f2,
+                                                               int32_t *__restrict__ force, double *__restrict__ rho_out,
+                                                               double *__restrict__ Xws, unsigned *nswap) {
+  __shared__ double red[kStrongThreads / kWave];
+  __shared__ int ired[2 * (kStrongThreads / kWave)];
+  extern __shared__ double om2[];  // [n] 1 / omega_i^2
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int64_t f0 = L.feat_off[j];
+  const int n = (int)(L.feat_off[j + 1] - f0);
+  const int m = (int)(L.row_off[j + 1] - L.row_off[j]);
+  const int r = rank[j];
+  for (int k = tid; k < n; k += kStrongThreads) force[f0 + k] = perm[f0 + k];
+  if (tid == 0) rho_out[j] = 0.0;
+  if (r == 0 || r >= n) return;
+  const double *__restrict__ R = Rout + L.rsq_off[j];  // R_hat(i, c) = R[c * n + i]
+  const double *__restrict__ Bq = Q + L.blk_off[j];    // slot column k, row i: Bq[k * m + i]
+  double *__restrict__ X = Xws + L.rsq_off[j];         // X(i, c) = X[c * r + i], c < r
+  for (int c = tid; c < r; c += kStrongThreads) {
+    for (int i = r - 1; i > c; --i) X[(int64_t)c * r + i] = 0.0;
+    for (int i = c; i >= 0; --i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= c; ++k) t -= R[(int64_t)k * n + i] * X[(int64_t)c * r + k];
+      X[(int64_t)c * r + i] = t / R[(int64_t)i * n + i];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += kStrongThreads) {
+    double t = 0.0;
+    for (int c = i; c < r; ++c) t += X[(int64_t)c * r + i] * X[(int64_t)c * r + i];
+    om2[i] = t;
+  }
+  __syncthreads();
+  double best = -1.0;
+  int bi = INT_MAX, bq = INT_MAX;
+  for (int q = tid; q < n - r; q += kStrongThreads) {
+    const double *col = Bq + (int64_t)(r + q) * m;
+    double g2 = 0.0;
+    for (int i = r; i < m; ++i) g2 += col[i] * col[i];
+    for (int i = 0; i < r; ++i) {
+      double w = 0.0;
+      for (int c = i; c < r; ++c) w += X[(int64_t)c * r + i] * col[c];
+      const double rho = w * w + g2 * om2[i];
+      if (rho > best || (rho == best && (i < bi || (i == bi && q < bq)))) {
+        best = rho;
+        bi = i;
+        bq = q;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, kWave);
+    const int oi = __shfl_xor(bi, off, kWave), oq = __shfl_xor(bq, off, kWave);
+    if (ob > best || (ob == best && (oi < bi || (oi == bi && oq < bq)))) {
+      best = ob;
+      bi = oi;
+      bq = oq;
+    }
+  }
+  if (lane == 0) {
+    red[wid] = best;
+    ired[2 * wid] = bi;
+    ired[2 * wid + 1] = bq;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    best = red[0];
+    bi = ired[0];
+    bq = ired[1];
+    for (int w = 1; w < kStrongThreads / kWave; ++w) {
+      const double ob = red[w];
+      const int oi = ired[2 * w], oq = ired[2 * w + 1];
+      if (ob > best || (ob == best && (oi < bi || (oi == bi && oq < bq)))) {
+        best = ob;
+        bi = oi;
+        bq = oq;
+      }
+    }
+    rho_out[j] = best;
+    if (best > f2 && bi < r && bq < n - r) {
+      force[f0 + bi] = perm[f0 + r + bq];
+      force[f0 + r + bq] = perm[f0 + bi];
+      atomicAdd(nswap, 1u);
+    }
+  }
 }
 
 rfm_status validate(const rfm_layout *L, const double *M, double tau, int32_t *rank, int32_t *kept, double *R,
@@ -441,8 +572,58 @@ extern "C" rfm_status rfm_rrqr_filter_tuned(const rfm_layout *L, const double *M
   if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
     return fail(RFM_EINVAL, "rfm_rrqr_filter: rrqr_threads must be 0, 256, 512 or 1024");
   Launch a{L, M, tau, rank, kept, R, Q, ratios, order, (unsigned *)ws, persistent,
-           tune ? tune->rrqr_wgs_per_cu : 1, (hipStream_t)stream};
+           tune ? tune->rrqr_wgs_per_cu : 1, (hipStream_t)stream, StrongIO{}};
   return dispatch(a, threads);
+}
+
+extern "C" size_t rfm_rrqr_strong_ws_bytes(const rfm_layout *L) {
+  if (!L) return 0;
+  // swap counter, two pivot orders, the R_hat inverses (64-byte aligned)
+  return 256 + 2 * (size_t)L->ncols * sizeof(int32_t) + 64 + (size_t)L->nrsq * sizeof(double);
+}
+
+extern "C" rfm_status rfm_rrqr_strong(const rfm_layout *L, const double *M, double tau, double f,
+                                      int32_t max_rounds, int32_t *rank, int32_t *kept, double *R, double *Q,
+                                      double *rho, int32_t *stats, void *ws, size_t ws_bytes, void *stream) {
+  using namespace rfm;
+  rfm_status s = validate(L, M, tau, rank, kept, R, Q, "rfm_rrqr_strong");
+  if (s != RFM_OK) return s;
+  if (!(f > 1.0)) return fail(RFM_EINVAL, "rfm_rrqr_strong: f must exceed 1");
+  if (max_rounds < 0) return fail(RFM_EINVAL, "rfm_rrqr_strong: max_rounds must be >= 0");
+  if (!rho || !stats) return fail(RFM_EINVAL, "rfm_rrqr_strong: null pointer");
+  if (!ws || ws_bytes < rfm_rrqr_strong_ws_bytes(L)) return fail(RFM_EINVAL, "rfm_rrqr_strong: workspace too small");
+  if ((size_t)L->max_cols * sizeof(double) > 64 * 1024)
+    return fail(RFM_EUNSUPPORTED, "rfm_rrqr_strong: max_cols too large");
+  hipStream_t st = (hipStream_t)stream;
+  char *p = (char *)ws;
+  unsigned *nswap = (unsigned *)p;
+  int32_t *perm = (int32_t *)(p + 256);
+  int32_t *force = perm + L->ncols;
+  double *X = (double *)(((uintptr_t)(force + L->ncols) + 63) & ~(uintptr_t)63);
+  // the plain filter (direct factorisation, norm-rule pivots) with the full pivot order out
+  Launch a{L, M, tau, rank, kept, R, Q, nullptr, nullptr, nullptr, 0, 1, st, StrongIO{perm, nullptr, nullptr}};
+  s = dispatch(a, 0);
+  if (s != RFM_OK) return s;
+  int32_t swaps = 0, rounds = 0;
+  const size_t lds = (size_t)L->max_cols * sizeof(double);
+  for (; rounds < max_rounds; ++rounds) {
+    RFM_HIP_TRY(hipMemsetAsync(nswap, 0, sizeof(unsigned), st));
+    hipLaunchKernelGGL(strong_check, dim3(L->J), dim3(kStrongThreads), lds, st, *L, (const int32_t *)rank,
+                       (const double *)R, (const double *)Q, (const int32_t *)perm, f * f, force, rho, X, nswap);
+    RFM_LAUNCH_CHECK();
+    unsigned h = 0;
+    RFM_HIP_TRY(hipMemcpyAsync(&h, nswap, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    RFM_HIP_TRY(hipStreamSynchronize(st));
+    if (h == 0) break;
+    swaps += (int32_t)h;
+    // refactor every block in its new order, keeping its rank
+    Launch b{L, M, tau, rank, kept, R, Q, nullptr, nullptr, nullptr, 0, 1, st, StrongIO{perm, force, rank}};
+    s = dispatch(b, 0);
+    if (s != RFM_OK) return s;
+  }
+  stats[0] = swaps;
+  stats[1] = rounds;
+  return RFM_OK;
 }
 
 extern "C" rfm_status rfm_plan_order(int32_t J, const int64_t *row_off, const int64_t *feat_off,

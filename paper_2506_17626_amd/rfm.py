@@ -326,6 +326,29 @@ def rfm_rrqr_filter(plan: Plan, M, tau, with_ratios=True, out=None, order=None, 
     return out
 
 
+_lib.rfm_rrqr_strong_ws_bytes.restype = C.c_size_t
+_lib.rfm_rrqr_strong_ws_bytes.argtypes = [C.POINTER(Layout)]
+_lib.rfm_rrqr_strong.restype = C.c_int
+_lib.rfm_rrqr_strong.argtypes = [C.POINTER(Layout), _p, C.c_double, C.c_double, C.c_int32, _p, _p, _p, _p, _p,
+                                 C.POINTER(C.c_int32), _p, C.c_size_t, _p]
+EXPORTED += ["rfm_rrqr_strong_ws_bytes", "rfm_rrqr_strong"]
+
+
+def rfm_rrqr_strong(plan: Plan, M, tau, f=2.0, max_rounds=32, out=None):
+    """Strong RRQR variant of the filter; returns (outputs with rho [J], swaps, rounds)."""
+    L = plan.layout
+    dev = M.device
+    out = _rrqr_out(L, dev, False) if out is None else out
+    out["rho"] = torch.zeros(max(L.J, 1), dtype=torch.float64, device=dev)
+    nb = _lib.rfm_rrqr_strong_ws_bytes(C.byref(L))
+    ws = _ws(nb, dev)
+    stats = (C.c_int32 * 2)()
+    _check(_lib.rfm_rrqr_strong(C.byref(L), _ptr(M), float(tau), float(f), int(max_rounds), _ptr(out["rank"]),
+                                _ptr(out["kept"]), _ptr(out["R"]), _ptr(out["Q"]), _ptr(out["rho"]), stats,
+                                _ptr(ws), nb, _stream()), "rfm_rrqr_strong")
+    return out, int(stats[0]), int(stats[1])
+
+
 def rfm_autotune(plan: Plan, M, tau, h, order=None, lsqr_iters=64, out=None):
     """Time the candidate launch shapes (filter, then the LSQR adjoint tile); returns
     (best Tuning, [(Tuning, ms)], filter outputs)."""
