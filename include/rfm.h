@@ -387,13 +387,16 @@ size_t rfm_evaluate_ws_bytes(const rfm_layout *L);
  * and while max rho > f^2 the pair (i, q) of the maximum is exchanged (kept column i for
  * trailing column q; ties to the smaller i, then q) and the block refactored in its new order
  * with the same rank, at most max_rounds rounds over all blocks (each round swaps once in
- * every block that needs it; |det A| grows by more than f per swap, so the loop ends).  On
- * return every block satisfies max rho <= f^2 unless stats[1] == max_rounds, and then
+ * every block that needs it; |det A| grows by more than f per swap, so the loop ends).  The
+ * test runs once more after the last round: on return every block satisfies max rho <= f^2
+ * unless stats[2] > 0 (max_rounds reached), and then
  * sigma_i(A) >= sigma_i(M_j) / sqrt(1 + f^2 r (n - r)) and
  * sigma_q(C) <= sigma_(r+q)(M_j) sqrt(1 + f^2 r (n - r)) (Gu and Eisenstat 1996).
  * Outputs as rfm_rrqr_filter (rank, kept in pivot order, R_hat, Q_hat; no ratios), plus
  * rho device [J]: the largest rho of the last test per block (0 where r is 0 or n_j), and
- * stats host [2]: total swaps, rounds taken.  f > 1.  Sync (one host read per round).
+ * stats host [3]: exchanges made, rounds taken, blocks whose last test still exceeds f^2
+ * (0 unless max_rounds stopped the loop).  f > 1, max_rounds >= 0 (0: the test only).
+ * Sync (one host read per test).
  * ws: rfm_rrqr_strong_ws_bytes(L) device bytes.  Needs max_rows <= 3072. */
 size_t rfm_rrqr_strong_ws_bytes(const rfm_layout *L);
 rfm_status rfm_rrqr_strong(const rfm_layout *L, const double *M, double tau, double f, int32_t max_rounds,

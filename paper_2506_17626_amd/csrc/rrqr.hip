@@ -604,9 +604,9 @@ extern "C" rfm_status rfm_rrqr_strong(const rfm_layout *L, const double *M, doub
   Launch a{L, M, tau, rank, kept, R, Q, nullptr, nullptr, nullptr, 0, 1, st, StrongIO{perm, nullptr, nullptr}};
   s = dispatch(a, 0);
   if (s != RFM_OK) return s;
-  int32_t swaps = 0, rounds = 0;
+  int32_t swaps = 0, rounds = 0, pending = 0;
   const size_t lds = (size_t)L->max_cols * sizeof(double);
-  for (; rounds < max_rounds; ++rounds) {
+  for (;;) {
     RFM_HIP_TRY(hipMemsetAsync(nswap, 0, sizeof(unsigned), st));
     hipLaunchKernelGGL(strong_check, dim3(L->J), dim3(kStrongThreads), lds, st, *L, (const int32_t *)rank,
                        (const double *)R, (const double *)Q, (const int32_t *)perm, f * f, force, rho, X, nswap);
@@ -614,8 +614,12 @@ extern "C" rfm_status rfm_rrqr_strong(const rfm_layout *L, const double *M, doub
     unsigned h = 0;
     RFM_HIP_TRY(hipMemcpyAsync(&h, nswap, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     RFM_HIP_TRY(hipStreamSynchronize(st));
-    if (h == 0) break;
+    if (h == 0 || rounds == max_rounds) {
+      pending = (int32_t)h;  // blocks whose last test still exceeded f^2
+      break;
+    }
     swaps += (int32_t)h;
+    ++rounds;
     // refactor every block in its new order, keeping its rank
     Launch b{L, M, tau, rank, kept, R, Q, nullptr, nullptr, nullptr, 0, 1, st, StrongIO{perm, force, rank}};
     s = dispatch(b, 0);
@@ -623,6 +627,7 @@ extern "C" rfm_status rfm_rrqr_strong(const rfm_layout *L, const double *M, doub
   }
   stats[0] = swaps;
   stats[1] = rounds;
+  stats[2] = pending;
   return RFM_OK;
 }
 

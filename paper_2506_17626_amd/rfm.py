@@ -335,17 +335,19 @@ EXPORTED += ["rfm_rrqr_strong_ws_bytes", "rfm_rrqr_strong"]
 
 
 def rfm_rrqr_strong(plan: Plan, M, tau, f=2.0, max_rounds=32, out=None):
-    """Strong RRQR variant of the filter; returns (outputs with rho [J], swaps, rounds)."""
+    """Strong RRQR variant of the filter; returns (outputs with rho [J] and pending = blocks
+    whose last test still exceeds f^2 when max_rounds stopped the loop, swaps, rounds)."""
     L = plan.layout
     dev = M.device
     out = _rrqr_out(L, dev, False) if out is None else out
     out["rho"] = torch.zeros(max(L.J, 1), dtype=torch.float64, device=dev)
     nb = _lib.rfm_rrqr_strong_ws_bytes(C.byref(L))
     ws = _ws(nb, dev)
-    stats = (C.c_int32 * 2)()
+    stats = (C.c_int32 * 3)()
     _check(_lib.rfm_rrqr_strong(C.byref(L), _ptr(M), float(tau), float(f), int(max_rounds), _ptr(out["rank"]),
                                 _ptr(out["kept"]), _ptr(out["R"]), _ptr(out["Q"]), _ptr(out["rho"]), stats,
                                 _ptr(ws), nb, _stream()), "rfm_rrqr_strong")
+    out["pending"] = int(stats[2])
     return out, int(stats[0]), int(stats[1])
 
 

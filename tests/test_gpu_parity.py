@@ -252,6 +252,7 @@ def test_strong_rrqr_matches_oracle(rfm, case, tau, f):
     M = _dev(H.pack_blocks(plan.host, blocks, K))
     out, swaps, rounds = rfm.rfm_rrqr_strong(plan, M, tau, f=f)
     torch.cuda.synchronize()
+    assert out.pop("pending") == 0
     o = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
     fo = plan.host["feat_off"]
     total, other = 0, []
@@ -286,6 +287,10 @@ def test_strong_rrqr_matches_oracle(rfm, case, tau, f):
         assert swaps == total
     if case == "kahan":
         assert swaps >= 1 and not other
+        # no rounds allowed: the test alone reports the Kahan block as pending and changes nothing
+        out0, sw0, rd0 = rfm.rfm_rrqr_strong(plan, M, tau, f=f, max_rounds=0)
+        assert sw0 == 0 and rd0 == 0 and out0["pending"] == 1
+        assert float(out0["rho"][2]) > f * f
 
 
 def _shared_factor_solve(rfm, inst, tau, atol, maxit=20000):
