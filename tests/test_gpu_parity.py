@@ -91,9 +91,11 @@ def test_assembly_matches_oracle(rfm, case):
     print(f"  worst entry error: {worst:.2f} u * E", flush=True)
 
 
-def test_assembly_full_size_sampled_blocks(rfm):
-    inst = I.workload("poisson2d")
-    print("[assembly] poisson2d full size, sampled blocks", flush=True)
+@pytest.mark.parametrize("case", [("poisson2d", "tanh", 1, 0), ("poisson2d", "sin", 1, 0),
+                                  ("poisson2d", "tanh", 3, 16), ("wave2d", "tanh", 1, 0)], ids=_case_id)
+def test_assembly_full_size_sampled_blocks(rfm, case):
+    inst = _instance(case, full=True)
+    print(f"[assembly] {inst.name} full size, sampled blocks", flush=True)
     plan, prob = _setup(rfm, inst)
     M, h = rfm.rfm_assemble(plan, prob)
     torch.cuda.synchronize()
@@ -101,15 +103,18 @@ def test_assembly_full_size_sampled_blocks(rfm):
     rows = assembly.incidence(inst)
     wins = assembly.windows(inst, rows)
     K = np.diff(inst.feat_off)
-    for j in (0, 15, 100, 137, 255):
+    G = None if inst.ansatz is None else inst.ansatz(inst.x)
+    for j in (0, 15, 100, 137, inst.J - 1):
         r = rows[j]
         w, dw, ddw = wins[j]
-        k0, k1 = inst.feat_off[j], inst.feat_off[j + 1]
-        phi, dphi, ddphi = assembly.features(inst.x[r], inst.mu[j], inst.hw[j], inst.w[k0:k1], inst.b[k0:k1])
+        phi, dphi, ddphi = assembly.block_features(inst, j, inst.x[r])
         psi = w[:, None] * phi
         dpsi = dw[:, None, :] * phi[:, :, None] + w[:, None, None] * dphi
         ddpsi = ddw[:, None, :] * phi[:, :, None] + 2.0 * dw[:, None, :] * dphi + w[:, None, None] * ddphi
-        ref = inst.weight[r][:, None] * assembly.apply_rowop(inst.rowop[r], psi, dpsi, ddpsi, inst.kappa, inst.ksq)
+        if G is not None:
+            psi, dpsi, ddpsi = assembly.with_ansatz(G[r], psi, dpsi, ddpsi)
+        ref = inst.weight[r][:, None] * assembly.apply_rowop(inst.rowop[r], psi, dpsi, ddpsi, inst.kappa, inst.ksq,
+                                                             inst.opcoef)
         got = H.unpack_block(Mh, plan.host, j, K)
         scale = assembly.entry_error_scale(inst, rows, j)
         assert np.all(np.abs(got - ref) <= 32 * U * scale)
