@@ -193,6 +193,48 @@ def test_rrqr_full_size_sampled_blocks(rfm, algo):
         assert np.max(np.abs(Rg - f.R)) <= 1e-12 * np.linalg.norm(blocks[j])
 
 
+def test_heat3d_full_size_sampled_assembly_and_filter(rfm):
+    """The (2+1)D heat workload at full size (512 blocks of about 2,600 x 300) in the launch
+    configuration the bench times (assembly, then the default filter at tau = 1e-12): sampled
+    blocks against the oracle, entries to 32 u E, rank and kept set exactly (ties at binary64
+    noise excepted), R_hat to 1e-12 ||M_j||."""
+    inst = I.workload("heat3d")
+    print("[pipeline] heat3d full size, sampled blocks", flush=True)
+    plan, prob = _setup(rfm, inst)
+    M, h = rfm.rfm_assemble(plan, prob)
+    fact = rfm.rfm_rrqr_filter(plan, M, 1e-12)
+    torch.cuda.synchronize()
+    rows = assembly.incidence(inst)
+    wins = assembly.windows(inst, rows)
+    K = np.diff(inst.feat_off)
+    ho = plan.host
+    rank = fact["rank"].cpu().numpy()
+    for j in (0, 77, 300, 511):
+        r_ = rows[j]
+        w, dw, ddw = wins[j]
+        phi, dphi, ddphi = assembly.block_features(inst, j, inst.x[r_])
+        psi = w[:, None] * phi
+        dpsi = dw[:, None, :] * phi[:, :, None] + w[:, None, None] * dphi
+        ddpsi = ddw[:, None, :] * phi[:, :, None] + 2.0 * dw[:, None, :] * dphi + w[:, None, None] * ddphi
+        ref = inst.weight[r_][:, None] * assembly.apply_rowop(inst.rowop[r_], psi, dpsi, ddpsi, inst.kappa, inst.ksq)
+        m = len(r_)
+        got = M[int(ho["blk_off"][j]):int(ho["blk_off"][j + 1])].cpu().numpy().reshape((m, int(K[j])), order="F")
+        assert np.all(np.abs(got - ref) <= 32 * U * assembly.entry_error_scale(inst, rows, j))
+        f = rrqr.qrcp_filter(ref, 1e-12)
+        r = int(rank[j])
+        kept = fact["kept"][int(ho["feat_off"][j]):int(ho["feat_off"][j]) + r].cpu().numpy()
+        if r != f.rank or not np.array_equal(kept, f.kept):
+            first = next((s for s in range(min(r, f.rank)) if kept[s] != f.kept[s]), min(r, f.rank))
+            margin = min(f.gaps[first] if first < len(f.gaps) else np.inf,
+                         abs(f.ratios[min(first, len(f.ratios) - 1)] - 1e-12))
+            assert margin < 1e-10, (j, r, f.rank, first, margin)
+            continue
+        Rg = fact["R"][int(ho["rsq_off"][j]):int(ho["rsq_off"][j + 1])].cpu().numpy()
+        Rg = Rg.reshape((int(K[j]), int(K[j])), order="F")[:r, :r]
+        assert np.max(np.abs(Rg - f.R)) <= 1e-12 * np.linalg.norm(ref)
+        print(f"  block {j}: {m} x {int(K[j])}, rank {r}", flush=True)
+
+
 @pytest.mark.parametrize("algo", sorted(ALGOS))
 def test_rrqr_edge_cases(rfm, algo):
     # a zero block, a duplicated column, a wide block, and a block with no rows
