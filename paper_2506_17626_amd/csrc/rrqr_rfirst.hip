@@ -823,6 +823,9 @@ __global__ __launch_bounds__(NT) void rf_formq1(rfm_layout L, const int32_t *__r
 }
 
 // ---------------------------------------------------------------- Q0 = H_0..H_{nr-1} [I; 0]
+// Every panel re-reads and rewrites the formed columns right of it, so the panel is as wide as
+// the LDS holds (not limited by registers, unlike the factorisation's panels).
+constexpr int kFormq0MaxNb = 32;
 // In place in the Q slot, backward over panels: the panel's reflectors go to LDS first, so
 // its columns can be overwritten; columns left of the panel still hold their reflectors.
 template <int T, int G>
@@ -837,8 +840,8 @@ __global__ __launch_bounds__(NT) void rf_formq0(rfm_layout L, const int32_t *__r
     const int m = B.m, nr = B.nr;
     if (rank[j] == 0) return;
     double *__restrict__ A = Q + B.base;
-    double *tl = lds;       // [nb]
-    double *Vp = lds + 16;  // [nb][ldv]
+    double *tl = lds;                 // [nb], nb <= kFormq0MaxNb
+    double *Vp = lds + kFormq0MaxNb;  // [nb][ldv]
     constexpr bool Q16 = T <= 12;     // one column per 16 lanes
     const int ldv = Q16 ? 64 * T : m;  // reflector rows zero-padded to 64 T in that case
     for (int p = ((nr - 1) / nb) * nb; p >= 0; p -= nb) {
@@ -1071,7 +1074,10 @@ rfm_status launch_tall(const RfirstArgs &a, const Ws &W, bool first) {
     if (s != RFM_OK) return s;
     hipLaunchKernelGGL(kern, grid, dim3(NT), lds, a.st, *L, a.M, a.Q, W.tau0, nb, a.order);
   } else {
-    const size_t lds = (16 + (size_t)nb * ldv) * sizeof(double);
+    int nbq = (int)((140 * 1024 - kFormq0MaxNb * sizeof(double)) / (ldv * sizeof(double)));
+    nbq = std::max(1, std::min(kFormq0MaxNb, nbq));
+    nb = nbq;
+    const size_t lds = (kFormq0MaxNb + (size_t)nb * ldv) * sizeof(double);
     auto kern = rf_formq0<T, GG>;
     rfm_status s = prep(kern, lds);
     if (s != RFM_OK) return s;
