@@ -122,6 +122,14 @@ __device__ __forceinline__ T activation1(int act, T s) {
   return tanh(s);
 }
 
+// The same with the activation fixed at compile time (kernels instantiated per activation).
+template <int ACT, typename T>
+__device__ __forceinline__ T activation1c(T s) {
+  if constexpr (ACT == RFM_ACT_SIN) return sin(s);
+  else if constexpr (ACT == RFM_ACT_SIGMOID) return (T)1 / ((T)1 + exp(-s));
+  else return tanh(s);
+}
+
 // Widest hidden layer of a depth-h feature network (held in registers per row).
 constexpr int kHMax = 16;
 constexpr int kMaxDepth = 8;

@@ -33,7 +33,7 @@ __device__ __forceinline__ double window_hat(const double *xr, const double *mu,
 }
 
 // Last hidden layer of a depth-h subdomain network at xn (values only; entries u >= H are 0).
-template <int D>
+template <int D, int ACT>
 __device__ __forceinline__ void hidden_value(const rfm_problem &P, int j, const double *xn, double (&z)[kHMax]) {
   const int H = P.hidden;
   const double *net = P.net + (int64_t)j * net_stride(P, D);
@@ -44,7 +44,7 @@ __device__ __forceinline__ void hidden_value(const rfm_problem &P, int j, const 
       double s = net[H * D + u];
 #pragma unroll
       for (int a = 0; a < D; ++a) s += net[u * D + a] * xn[a];
-      z[u] = activation1<double>(P.activation, s);
+      z[u] = activation1c<ACT, double>(s);
     }
   }
   net += H * D + H;
@@ -58,7 +58,7 @@ __device__ __forceinline__ void hidden_value(const rfm_problem &P, int j, const 
 #pragma unroll
         for (int v = 0; v < kHMax; ++v)
           if (v < H) s += net[u * H + v] * z[v];
-        nz[u] = activation1<double>(P.activation, s);
+        nz[u] = activation1c<ACT, double>(s);
       }
     }
 #pragma unroll
@@ -66,7 +66,7 @@ __device__ __forceinline__ void hidden_value(const rfm_problem &P, int j, const 
   }
 }
 
-template <int D, bool DEEP>
+template <int D, bool DEEP, int ACT>
 __global__ __launch_bounds__(kEvalThreads) void eval_points(rfm_layout L, rfm_problem P, const double *__restrict__ a,
                                                             double *__restrict__ uhat,
                                                             const double *__restrict__ ue, double *part) {
@@ -95,21 +95,21 @@ __global__ __launch_bounds__(kEvalThreads) void eval_points(rfm_layout L, rfm_pr
       double acc = 0.0;
       if constexpr (DEEP) {
         double z[kHMax];
-        hidden_value<D>(P, j, xn, z);
+        hidden_value<D, ACT>(P, j, xn, z);
         const int H = P.hidden;
         for (int64_t k = f0; k < f1; ++k) {
           double s = P.b[k];
 #pragma unroll
           for (int u = 0; u < kHMax; ++u)
             if (u < H) s += P.w[k * H + u] * z[u];
-          acc += a[k] * activation1<double>(P.activation, s);
+          acc += a[k] * activation1c<ACT, double>(s);
         }
       } else {
         for (int64_t k = f0; k < f1; ++k) {
           double s = P.b[k];
 #pragma unroll
           for (int i = 0; i < D; ++i) s += xn[i] * P.w[k * D + i];
-          acc += a[k] * activation1<double>(P.activation, s);
+          acc += a[k] * activation1c<ACT, double>(s);
         }
       }
       u += w * acc;
@@ -156,10 +156,17 @@ template <int D>
 rfm_status launch_eval(const rfm_layout *L, const rfm_problem *P, const double *a, double *uhat, const double *ue,
                        double *part, double *sums, hipStream_t st) {
   const unsigned g = ceil_div(L->N, kEvalThreads);
-  if (P->depth > 1)
-    hipLaunchKernelGGL((eval_points<D, true>), dim3(g), dim3(kEvalThreads), 0, st, *L, *P, a, uhat, ue, part);
-  else
-    hipLaunchKernelGGL((eval_points<D, false>), dim3(g), dim3(kEvalThreads), 0, st, *L, *P, a, uhat, ue, part);
+  const bool deep = P->depth > 1;
+#define RFM_EVAL(DP, ACT) \
+  hipLaunchKernelGGL((eval_points<D, DP, ACT>), dim3(g), dim3(kEvalThreads), 0, st, *L, *P, a, uhat, ue, part)
+  if (P->activation == RFM_ACT_SIN) {
+    if (deep) RFM_EVAL(true, RFM_ACT_SIN); else RFM_EVAL(false, RFM_ACT_SIN);
+  } else if (P->activation == RFM_ACT_SIGMOID) {
+    if (deep) RFM_EVAL(true, RFM_ACT_SIGMOID); else RFM_EVAL(false, RFM_ACT_SIGMOID);
+  } else {
+    if (deep) RFM_EVAL(true, RFM_ACT_TANH); else RFM_EVAL(false, RFM_ACT_TANH);
+  }
+#undef RFM_EVAL
   RFM_LAUNCH_CHECK();
   if (ue) {
     hipLaunchKernelGGL(eval_reduce, dim3(1), dim3(1024), 0, st, part, (int64_t)g, 2, sums);
