@@ -132,3 +132,50 @@ def test_plan_order_sorts_by_factorisation_cost():
     for a, b in zip(order[:-1], order[1:]):
         if cost[a] == cost[b]:
             assert a < b
+
+
+def _host_layout(rfm, inst):
+    """A layout whose array fields point at host copies (non-null, never dereferenced: every
+    call below fails validation before any device work)."""
+    plan = rfm.plan_instance(inst, device=None)
+    L = plan.layout
+    for k in ("row_off", "rows", "inc_blk", "rinc_off", "rinc", "feat_off", "blk_off", "rsq_off"):
+        setattr(L, k, plan.host[k].ctypes.data)
+    return plan, L
+
+
+def test_variant_arguments_rejected_without_device_work():
+    from paper_2506_17626_amd import rfm
+    lib = rfm._lib
+    inst = I.tiny("poisson1d")
+    plan, L = _host_layout(rfm, inst)
+    fake = C.c_void_p(plan.host["rows"].ctypes.data)
+    stats = (C.c_int32 * 3)()
+    nb = lib.rfm_rrqr_strong_ws_bytes(C.byref(L))
+    assert nb > 0
+    args = lambda f, rounds, ws_bytes: (C.byref(L), fake, 1e-8, f, rounds, fake, fake, fake, fake, fake, stats,
+                                        fake, ws_bytes, None)
+    assert lib.rfm_rrqr_strong(*args(1.0, 4, nb)) == rfm.RFM_EINVAL
+    assert b"f must exceed 1" in lib.rfm_last_error()
+    assert lib.rfm_rrqr_strong(*args(2.0, -1, nb)) == rfm.RFM_EINVAL
+    assert lib.rfm_rrqr_strong(*args(2.0, 4, nb - 1)) == rfm.RFM_EINVAL
+    assert b"workspace" in lib.rfm_last_error()
+
+    def problem(**kw):
+        p = rfm.Problem(x=fake, rowop=fake, weight=fake, rhs=fake, mu=fake, hw=fake, w=fake, b=fake)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    anb = lib.rfm_assemble_ws_bytes(C.byref(L))
+    for kw, msg in ((dict(activation=7), b"unknown activation"), (dict(depth=9), b"depth out of range"),
+                    (dict(depth=3, hidden=17, net=fake), b"hidden width"),
+                    (dict(depth=3, hidden=8, net=None), b"hidden width"),
+                    (dict(nopcoef=2, opcoef=None), b"operator table"), (dict(nopcoef=-1), b"operator table")):
+        P = problem(**kw)
+        assert lib.rfm_assemble(C.byref(L), C.byref(P), fake, fake, fake, anb, None) == rfm.RFM_EINVAL, kw
+        assert msg in lib.rfm_last_error(), (kw, lib.rfm_last_error())
+    enb = lib.rfm_evaluate_ws_bytes(C.byref(L))
+    P = problem(activation=3)
+    assert lib.rfm_evaluate(C.byref(L), C.byref(P), fake, fake, None, None, fake, enb, None) == rfm.RFM_EINVAL
+    assert b"unknown activation" in lib.rfm_last_error()
