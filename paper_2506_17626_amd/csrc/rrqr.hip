@@ -420,9 +420,11 @@ rfm_status dispatch(const Launch &a, int threads) {
 // For block j with 0 < r < n after a factorisation that left R_hat (r x r, positive diagonal)
 // in the R slot and the trailing columns [B; C] (sign-consistent with R_hat) in the Q slot,
 // in position order perm:
-//   X = R_hat^-1 (column c by back-substitution, one thread per column, into the block's R-sized
-//   slot of the workspace), 1/omega_i^2 = sum_c X_ic^2, W = X B, gamma_q = ||C e_q||, and
-//   rho_iq = W_iq^2 + gamma_q^2 / omega_i^2.
+//   X = R_hat^-1, upper triangular, row-major in the block's R-sized slot of the workspace,
+//   formed a row at a time from the last (row i of R_hat staged in LDS; the entries of row i
+//   of X are independent given rows > i, one thread per column, coalesced reads of X);
+//   1/omega_i^2 = ||row i of X||^2 (a wave per row), gamma_q^2 = ||C e_q||^2 (a wave per
+//   trailing column), and rho_iq = (X B)_iq^2 + gamma_q^2 / omega_i^2 over all (i, q) pairs.
 // The largest rho (ties: smaller i, then smaller q) is the candidate swap of Gu and
 // Eisenstat's strong RRQR; if it exceeds f^2 the block's next pivot order is perm with
 // positions i and r + q exchanged (and the swap counter is raised), else perm itself.
@@ -434,9 +436,10 @@ __global__ __launch_bounds__(kStrongThreads) void strong_check(rfm_layout L, con
                                                                const int32_t *__restrict__ perm, double f2,
                                                                int32_t *__restrict__ force, double *__restrict__ rho_out,
                                                                double *__restrict__ Xws, unsigned *nswap) {
-  __shared__ double red[kStrongThreads / kWave];
-  __shared__ int ired[2 * (kStrongThreads / kWave)];
-  extern __shared__ double om2[];  // [n] 1 / omega_i^2
+  constexpr int NW = kStrongThreads / kWave;
+  __shared__ double red[NW];
+  __shared__ int ired[2 * NW];
+  extern __shared__ double sm[];  // arow [n], om2 [n], g2 [n]
   const int j = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int64_t f0 = L.feat_off[j];
@@ -446,39 +449,52 @@ __global__ __launch_bounds__(kStrongThreads) void strong_check(rfm_layout L, con
   for (int k = tid; k < n; k += kStrongThreads) force[f0 + k] = perm[f0 + k];
   if (tid == 0) rho_out[j] = 0.0;
   if (r == 0 || r >= n) return;
+  double *arow = sm, *om2 = sm + n, *g2 = sm + 2 * n;
+  const int nt = n - r;
   const double *__restrict__ R = Rout + L.rsq_off[j];  // R_hat(i, c) = R[c * n + i]
   const double *__restrict__ Bq = Q + L.blk_off[j];    // slot column k, row i: Bq[k * m + i]
-  double *__restrict__ X = Xws + L.rsq_off[j];         // X(i, c) = X[c * r + i], c < r
-  for (int c = tid; c < r; c += kStrongThreads) {
-    for (int i = r - 1; i > c; --i) X[(int64_t)c * r + i] = 0.0;
-    for (int i = c; i >= 0; --i) {
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= c; ++k) t -= R[(int64_t)k * n + i] * X[(int64_t)c * r + k];
-      X[(int64_t)c * r + i] = t / R[(int64_t)i * n + i];
+  double *__restrict__ X = Xws + L.rsq_off[j];         // X(i, c) = X[i * r + c]
+  for (int i = r - 1; i >= 0; --i) {
+    for (int k = i + tid; k < r; k += kStrongThreads) arow[k] = R[(int64_t)k * n + i];
+    __syncthreads();
+    const double inv = 1.0 / arow[i];
+    for (int c = tid; c < r; c += kStrongThreads) {
+      double t = 0.0;
+      if (c >= i) {
+        t = (c == i) ? 1.0 : 0.0;
+        for (int k = i + 1; k <= c; ++k) t -= arow[k] * X[(int64_t)k * r + c];
+        t *= inv;
+      }
+      X[(int64_t)i * r + c] = t;
     }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int i = tid; i < r; i += kStrongThreads) {
+  for (int i = wid; i < r; i += NW) {
     double t = 0.0;
-    for (int c = i; c < r; ++c) t += X[(int64_t)c * r + i] * X[(int64_t)c * r + i];
-    om2[i] = t;
+    for (int c = i + lane; c < r; c += kWave) t += X[(int64_t)i * r + c] * X[(int64_t)i * r + c];
+    t = wave_sum(t);
+    if (lane == 0) om2[i] = t;
+  }
+  for (int q = wid; q < nt; q += NW) {
+    const double *col = Bq + (int64_t)(r + q) * m;
+    double t = 0.0;
+    for (int i = r + lane; i < m; i += kWave) t += col[i] * col[i];
+    t = wave_sum(t);
+    if (lane == 0) g2[q] = t;
   }
   __syncthreads();
   double best = -1.0;
   int bi = INT_MAX, bq = INT_MAX;
-  for (int q = tid; q < n - r; q += kStrongThreads) {
+  for (int64_t e = tid; e < (int64_t)r * nt; e += kStrongThreads) {
+    const int i = (int)(e / nt), q = (int)(e % nt);
     const double *col = Bq + (int64_t)(r + q) * m;
-    double g2 = 0.0;
-    for (int i = r; i < m; ++i) g2 += col[i] * col[i];
-    for (int i = 0; i < r; ++i) {
-      double w = 0.0;
-      for (int c = i; c < r; ++c) w += X[(int64_t)c * r + i] * col[c];
-      const double rho = w * w + g2 * om2[i];
-      if (rho > best || (rho == best && (i < bi || (i == bi && q < bq)))) {
-        best = rho;
-        bi = i;
-        bq = q;
-      }
+    double w = 0.0;
+    for (int c = i; c < r; ++c) w += X[(int64_t)i * r + c] * col[c];
+    const double rho = w * w + g2[q] * om2[i];
+    if (rho > best || (rho == best && (i < bi || (i == bi && q < bq)))) {
+      best = rho;
+      bi = i;
+      bq = q;
     }
   }
 #pragma unroll
@@ -501,7 +517,7 @@ __global__ __launch_bounds__(kStrongThreads) void strong_check(rfm_layout L, con
     best = red[0];
     bi = ired[0];
     bq = ired[1];
-    for (int w = 1; w < kStrongThreads / kWave; ++w) {
+    for (int w = 1; w < NW; ++w) {
       const double ob = red[w];
       const int oi = ired[2 * w], oq = ired[2 * w + 1];
       if (ob > best || (ob == best && (oi < bi || (oi == bi && oq < bq)))) {
@@ -511,7 +527,7 @@ __global__ __launch_bounds__(kStrongThreads) void strong_check(rfm_layout L, con
       }
     }
     rho_out[j] = best;
-    if (best > f2 && bi < r && bq < n - r) {
+    if (best > f2 && bi < r && bq < nt) {
       force[f0 + bi] = perm[f0 + r + bq];
       force[f0 + r + bq] = perm[f0 + bi];
       atomicAdd(nswap, 1u);
@@ -592,7 +608,7 @@ extern "C" rfm_status rfm_rrqr_strong(const rfm_layout *L, const double *M, doub
   if (max_rounds < 0) return fail(RFM_EINVAL, "rfm_rrqr_strong: max_rounds must be >= 0");
   if (!rho || !stats) return fail(RFM_EINVAL, "rfm_rrqr_strong: null pointer");
   if (!ws || ws_bytes < rfm_rrqr_strong_ws_bytes(L)) return fail(RFM_EINVAL, "rfm_rrqr_strong: workspace too small");
-  if ((size_t)L->max_cols * sizeof(double) > 64 * 1024)
+  if (3 * (size_t)L->max_cols * sizeof(double) > 64 * 1024)
     return fail(RFM_EUNSUPPORTED, "rfm_rrqr_strong: max_cols too large");
   hipStream_t st = (hipStream_t)stream;
   char *p = (char *)ws;
@@ -605,7 +621,7 @@ extern "C" rfm_status rfm_rrqr_strong(const rfm_layout *L, const double *M, doub
   s = dispatch(a, 0);
   if (s != RFM_OK) return s;
   int32_t swaps = 0, rounds = 0, pending = 0;
-  const size_t lds = (size_t)L->max_cols * sizeof(double);
+  const size_t lds = 3 * (size_t)L->max_cols * sizeof(double);
   for (;;) {
     RFM_HIP_TRY(hipMemsetAsync(nswap, 0, sizeof(unsigned), st));
     hipLaunchKernelGGL(strong_check, dim3(L->J), dim3(kStrongThreads), lds, st, *L, (const int32_t *)rank,
