@@ -1063,9 +1063,11 @@ rfm_status launch_tall(const RfirstArgs &a, const Ws &W, bool first) {
   const dim3 grid((unsigned)L->J);
   // reflector rows in LDS: zero-padded to 64 T for the 16-lane layout (T <= 12), else
   // max_rows; panel width nb from the LDS budget, at most the panel columns the waves hold in
-  // registers
+  // registers (the tall blocks of the 3D workload, 2,744 rows, fit 7 reflectors)
   const size_t ldv = (T <= 12) ? (size_t)64 * T : (size_t)std::max(1, L->max_rows);
-  int nb = (int)((140 * 1024 - (size_t)L->max_cols * sizeof(double)) / (ldv * sizeof(double)));
+  // dynamic LDS for the reflector panels: all but 2 KB of the 160 KB a workgroup may take
+  constexpr size_t tall_lds = 158 * 1024;
+  int nb = (int)((tall_lds - (size_t)L->max_cols * sizeof(double)) / (ldv * sizeof(double)));
   nb = std::max(1, std::min(npc_of(T) * NW, nb));
   if (first) {
     const size_t lds = ((size_t)L->max_cols + (size_t)nb * ldv) * sizeof(double);
@@ -1074,7 +1076,7 @@ rfm_status launch_tall(const RfirstArgs &a, const Ws &W, bool first) {
     if (s != RFM_OK) return s;
     hipLaunchKernelGGL(kern, grid, dim3(NT), lds, a.st, *L, a.M, a.Q, W.tau0, nb, a.order);
   } else {
-    int nbq = (int)((140 * 1024 - kFormq0MaxNb * sizeof(double)) / (ldv * sizeof(double)));
+    int nbq = (int)((tall_lds - kFormq0MaxNb * sizeof(double)) / (ldv * sizeof(double)));
     nbq = std::max(1, std::min(kFormq0MaxNb, nbq));
     nb = nbq;
     const size_t lds = (kFormq0MaxNb + (size_t)nb * ldv) * sizeof(double);
