@@ -30,7 +30,7 @@ namespace {
 
 constexpr int NT = 512;
 constexpr int NW = NT / kWave;
-constexpr size_t kLdsCap = 150 * 1024;
+constexpr size_t kLdsCap = 158 * 1024;
 
 struct Blk {
   int m, n, nr;
