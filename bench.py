@@ -470,7 +470,8 @@ def learned_study(args):
                                progress=lambda d, n: note(f"training solves {d}/{n}"))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    model = learned.train_warm_start(ts, hidden=512, epochs=args.epochs, batch=256, lr=1e-3, seed=args.seed)
+    model = learned.train_warm_start(ts, hidden=512, epochs=args.epochs, batch=min(256, args.n_train), lr=1e-3,
+                                     seed=args.seed)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     note(f"trained {args.epochs} epochs, loss {model.loss_history[0]:.3e} -> {model.loss_history[-1]:.3e}")
