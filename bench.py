@@ -626,13 +626,16 @@ def main():
         if record is not None:
             record.append((ev, kt, info))
 
-    for _ in range(args.warmup):
+    # a progress line per step on stderr (a step of the large workloads takes minutes)
+    for k in range(args.warmup):
         step(None)
+        print(f"[bench] {args.workload}: warm-up step {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step(recs)
+        print(f"[bench] {args.workload}: step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
