@@ -602,6 +602,8 @@ def main():
     gt = rfm.evaluation_ansatz(inst, xt)
     ews = torch.empty(rfm._lib.rfm_evaluate_ws_bytes(rfm.C.byref(tplan.layout)), dtype=torch.uint8, device=dev)
     e_l1 = []
+    print(f"[bench] {args.workload}: {inst.J} blocks, {L.N} rows, {L.ncols} columns planned", file=sys.stderr,
+          flush=True)
 
     E = lambda: torch.cuda.Event(enable_timing=True)
     phases = ("assemble", "rrqr", "lsqr", "coefficients", "evaluate")
