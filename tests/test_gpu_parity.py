@@ -355,8 +355,13 @@ def _shared_factor_solve(rfm, inst, tau, atol, maxit=20000):
     return plan, facts, fact, A, h, y_or, info_or, y, info
 
 
-@pytest.mark.parametrize("name", ["poisson1d", "poisson2d", "heat3d"])
+@pytest.mark.parametrize("name", ["poisson1d", "poisson2d", "heat3d", "oscillator1d", "laplace2d_multiscale",
+                                  "wave2d"])
 def test_lsqr_shared_factors_matches_oracle(rfm, name):
+    """Both sides run the same rule (atol = btol = 1e-12) on the oracle's factors and stop at
+    nearby iterations; y agrees to 1e-8 relative, or, on the paper's problems, whose operators
+    reach kappa ~ 1e5-1e6 on these instances, to 4 kappa (atol + btol): what the rule itself
+    leaves undetermined in y."""
     inst = I.tiny(name)
     print(f"[lsqr] {name}", flush=True)
     plan, facts, fact, A, h, y_or, info_or, y, info = _shared_factor_solve(rfm, inst, 1e-10, 1e-12)
@@ -365,10 +370,18 @@ def test_lsqr_shared_factors_matches_oracle(rfm, name):
     rel = np.linalg.norm(yg - ypad) / np.linalg.norm(ypad)
     print(f"  iters gpu {info.iters} oracle {info_or.iters}; stop {info.stop}/{info_or.stop}; rel {rel:.2e}; "
           f"relres {info.relres:.3e} eta {info.eta:.3e}", flush=True)
-    assert rel <= 1e-8
+    paper = name in ("oscillator1d", "laplace2d_multiscale", "wave2d")
+    tol = 1e-8
+    if paper:
+        D = np.stack([A.matvec(e) for e in np.eye(A.n)], axis=1)
+        tol = max(tol, 4 * np.linalg.cond(D) * 2e-12)
+    assert rel <= tol, (rel, tol)
     assert info.stop in (1, 2, 4)
     relres_or, eta_or = olsqr.explicit_residuals(A, h, y_or)
-    assert info.relres == pytest.approx(relres_or, rel=1e-6, abs=1e-14)
+    if paper:  # consistent systems stopped near the noise floor at different iterations
+        assert abs(info.relres - relres_or) <= 1e-10, (info.relres, relres_or)
+    else:
+        assert info.relres == pytest.approx(relres_or, rel=1e-6, abs=1e-14)
 
 
 def test_lsqr_iterates_track_oracle_in_early_iterations(rfm):
@@ -564,7 +577,9 @@ def test_pack_q_rounding_bitwise(rfm, name):
 
 
 @pytest.mark.parametrize("dtype,name,tau", [("f32", "heat3d", 1e-10), ("f32", "poisson1d", 1e-8),
-                                            ("bf16", "poisson2d", 1e-1), ("bf16", "heat3d", 1e-10)])
+                                            ("bf16", "poisson2d", 1e-1), ("bf16", "heat3d", 1e-10),
+                                            ("f32", "oscillator1d", 1e-8), ("f32", "laplace2d_multiscale", 1e-8),
+                                            ("f32", "wave2d", 1e-8)])
 def test_precision_form_reaches_binary64_solution(rfm, dtype, name, tau):
     """Refinement around the narrow operator plus the binary64 finish gives the binary64
     least-squares solution (compared with the oracle's dense solve)."""
